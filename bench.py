@@ -1,0 +1,192 @@
+"""Throughput of the m-Cubes VEGAS sampling path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tables|corner8|gauss8|small]
+
+One step is one complete m-Cubes run (mc_integrate: every iteration of
+sampling kernel + fixed-order reduction + read-back + host weighting, bin
+adjustment and convergence check) on the workload's synthetic inputs; the
+device workspace is allocated before the timed region.  `value` is integrand
+samples per second over the K timed steps (iterations * m * p per step).
+
+The roofline entry is for the sampling kernel: its average launch duration
+comes from HIP events recorded by the library on the launch stream, and its
+algorithmic work is the per-sample VALU lane-operation count of the method's
+steps (quarter-rate operations weighted 4), times the samples per launch,
+against the chip's VALU issue rate.  The CPU baseline times the FP64 oracle on
+one host core over a bounded block of sub-cubes of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = VALU lane-op issue rate.
+CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
+VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 lane-ops/s
+
+
+def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
+    """Algorithmic VALU lane-operations per sample (quarter-rate ops count 4).
+
+    Per sample: ceil(d/2) Philox4x32-10 blocks (19 vector 32x32->64 products
+    at 4 + 39 XOR), per axis 20 (uniform 5, stratified coordinate 2, bin index
+    and clamp 7, boundary address and width 2, point 2, Jacobian 2), the
+    integrand, 3 for f*J/(mp) and the finiteness check, 3 (p-1)/p for the
+    shifted sums, 1 + d for the bin-contribution addresses when adjusting, and
+    per sub-cube (18 + 5d)/p for the variance, two compensated additions and
+    the digit odometer.  Integrands: Gaussian 3d + 20 (exp), corner peak
+    d + popcount-powering + 10 (division), tables = Gaussian + 2 x 21 + 2.
+    """
+    d = int(prob["dim"])
+    _, _, p = g_m_p
+    kind = prob["integrand"]
+    philox = math.ceil(d / 2) * (19 * 4 + 39)
+    per_axis = 20 * d
+    if kind == "const":
+        f = 0
+    elif kind == "gauss_product":
+        f = 3 * d + 20
+    elif kind == "corner_peak":
+        e = d + 1
+        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + 10
+    else:
+        f = 3 * d + 20 + 2 * 21 + 2
+    tail = 3 + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (18 + 5 * d) / p
+    return float(philox + per_axis + f + tail)
+
+
+WORKLOADS = {
+    "tables": ("gauss_tables_d6_1e8", lambda W, seed: W.config_tables(seed=seed)),
+    "small": ("gauss_product_d2_1e4", lambda W, seed: W.config_small(seed=seed)),
+    "corner8": ("corner_peak_d8_1e9", lambda W, seed: W.config_corner8(seed=seed)),
+    "gauss8": ("gauss_product_d8_w0.01_1e9", lambda W, seed: W.config_gauss8(seed=seed)),
+}
+
+
+def cpu_baseline(prob, target_s: float = 12.0):
+    """Times the oracle's V-Sample on one core over the first sub-cubes of iteration 0."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+
+    d, nb = prob["dim"], prob["nbins"]
+    g, m, p = O.shape(d, prob["maxcalls"])
+    grid = O.init_grid(d, nb)
+    n = min(m, 20_000)
+    t = time.perf_counter()
+    O.vsample(prob, 0, grid, 0, n, hist=True)
+    dt = time.perf_counter() - t
+    n2 = int(min(m, max(n, n * target_s / max(dt, 1e-6))))
+    t = time.perf_counter()
+    O.vsample(prob, 0, grid, 0, n2, hist=True)
+    dt = time.perf_counter() - t
+    return {"value": n2 * p / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"one V-Sample pass (iteration 0, uniform grid, histogram on) over "
+                      f"sub-cubes [0, {n2}) of {m} = {n2 * p} samples, {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tables", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2202_01753_amd import mcubes as M
+    from paper_2202_01753_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    name, make = WORKLOADS[args.workload]
+    prob = make(W, 1)
+    bp = M.BoundProblem(prob, args.blocks, args.threads)
+    ws = M.Workspace(bp)
+    gmp = M.shape(prob["dim"], prob["maxcalls"])
+    calls_per_iter = gmp[1] * gmp[2]
+
+    def step(seed):
+        prob["seed"] = seed
+        bp.s.seed = seed
+        return M.integrate(prob, ws=ws, bp=bp, timing=True)
+
+    for w in range(args.warmup):
+        step(1000 + w)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        results.append(step(1 + k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    calls = sum(r.calls for r in results)
+    launches = sum(r.iterations for r in results)
+    sample_ms = sum(r.sample_ms for r in results)
+    fin_ms = sum(r.finalize_ms for r in results)
+    avg_launch_s = sample_ms / launches / 1e3
+    ops = ops_per_sample(prob, gmp, adjust=prob["ita"] > 0) * calls_per_iter
+    achieved = ops / avg_launch_s
+    r0 = results[0]
+
+    # time to a 1e-3 relative error on the same workload (FP64 path)
+    prob_t = dict(prob)
+    prob_t["tau_rel"] = 1e-3
+    bpt = M.BoundProblem(prob_t, args.blocks, args.threads)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rt = M.integrate(prob_t, ws=ws, bp=bpt)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t1
+
+    line = {
+        "metric": "integrand samples/sec/GPU",
+        "value": calls / elapsed,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "dim": prob["dim"], "maxcalls": prob["maxcalls"],
+                   "calls_per_iter": calls_per_iter, "nbins": prob["nbins"],
+                   "itmax": prob["itmax"], "alpha": prob["alpha"],
+                   "step": "one full m-Cubes run (mc_integrate)"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "vsample_kernel", "avg_launch_ms": avg_launch_s * 1e3,
+                     "ops_per_sample": ops / calls_per_iter,
+                     "launch": {"blocks": r0.blocks, "threads": r0.threads,
+                                "lds_bytes": r0.lds_bytes}},
+        "kernel_samples_per_s": calls_per_iter / avg_launch_s,
+        "finalize_ms_per_iter": fin_ms / launches,
+        "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
+                         "estimate": rt.estimate, "rel_error": rt.error / abs(rt.estimate)},
+        "estimate": {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * mcubes.h - C ABI of the MI355X (gfx950) m-Cubes VEGAS integrator.
+ *
+ * The library implements the method of Sakiotis et al., "m-Cubes: An
+ * Efficient and Portable Implementation of Multi-Dimensional Integration for
+ * GPUs" (arXiv 2202.01753): the m-Cubes driver (Alg. 2) on the host and the
+ * V-Sample / V-Sample-No-Adjust sampling pass (Alg. 3, Sec. IV) as HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - All functions return an mc_status; nothing else crosses the boundary on
+ *     error, and output arguments are left untouched when the status is not
+ *     MC_OK.
+ *   - "host" pointers are ordinary CPU memory, borrowed for the duration of
+ *     the call (the library copies what it keeps).  "device" pointers are
+ *     GPU memory on the current HIP device, owned by the caller.
+ *   - The library never allocates device memory: the caller provides a
+ *     workspace of at least mc_workspace_bytes() bytes.  Streams are
+ *     hipStream_t values passed as void* (NULL = the default stream).
+ *   - Calls are reentrant across distinct workspaces; two calls that share a
+ *     workspace must not overlap.
+ *   - Integration domains are boxes [lo_j, hi_j]; the adaptive grid lives in
+ *     unit coordinates and is d rows of nbins+1 boundaries (row j = axis j,
+ *     boundary 0 is 0.0 and boundary nbins is 1.0).
+ */
+#ifndef MCUBES_H
+#define MCUBES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mc_status;
+#define MC_OK 0
+#define MC_EINVAL 1      /* invalid problem or argument; checked before any device work */
+#define MC_EWORKSPACE 2  /* workspace smaller than mc_workspace_bytes() */
+#define MC_ENONFINITE 3  /* the integrand produced a NaN or an infinity */
+#define MC_EDEVICE 4     /* a HIP runtime error (no device, launch failure, ...) */
+
+/* Integrand ids.  Parameter layouts (n_params doubles):
+ *   MC_F_CONST          [v]                   f = v
+ *   MC_F_GAUSS_PRODUCT  [c_1..c_d, w_1..w_d]  f = exp(-sum_j ((x_j - c_j)/w_j)^2)
+ *   MC_F_CORNER_PEAK    [a_1..a_d]            f = (1 + sum_j a_j x_j)^-(d+1)
+ *   MC_F_GAUSS_TABLES   [c_1..c_d, w_1..w_d]  f = gauss_product * T1(x_1,x_2) * T2(x_3,x_4)
+ * The last one needs d >= 4 and two 256x256 row-major FP64 tables (n_tables =
+ * 131072), node (a,b) at (a/255, b/255), bilinear inside a cell and extended
+ * from the edge cell outside the unit square.  The Gaussian and corner-peak
+ * forms are the product-peak / Gaussian and corner-peak families of the
+ * paper's test suite (Sec. V, eqs. 3-4). */
+#define MC_F_CONST 0
+#define MC_F_GAUSS_PRODUCT 1
+#define MC_F_CORNER_PEAK 2
+#define MC_F_GAUSS_TABLES 3
+
+#define MC_FP64 0 /* all arithmetic in FP64 */
+
+#define MC_MAX_DIM 16
+
+/* An integration problem: the inputs of the m-Cubes procedure (Alg. 2:
+ * f, d, nb, maxcalls, L, H, itmax, ita) plus the damping exponent of the bin
+ * adjustment, the target relative error of the convergence check (Sec. V) and
+ * the seed of the counter-based random numbers. */
+typedef struct mc_problem {
+    int32_t integrand;       /* MC_F_* */
+    int32_t dim;             /* d, 1..MC_MAX_DIM */
+    const double *params;    /* host, n_params doubles (layout above) */
+    int64_t n_params;
+    const double *tables;    /* host, n_tables doubles, or NULL */
+    int64_t n_tables;
+    const double *lo;        /* host, dim doubles, finite */
+    const double *hi;        /* host, dim doubles, finite, hi > lo */
+    int64_t maxcalls;        /* samples per iteration budget, >= 4 */
+    int32_t nbins;           /* nb, bins per axis, >= 2 */
+    int32_t itmax;           /* iterations, >= 1 */
+    int32_t ita;             /* adjusting iterations, 0..itmax */
+    int32_t precision;       /* MC_FP64 */
+    double alpha;            /* damping exponent of the bin adjustment, > 0 */
+    double tau_rel;          /* target relative error; 0 runs all itmax iterations */
+    uint64_t seed;           /* random-number key */
+    int32_t blocks;          /* workgroups of the sampling kernel; 0 = fill the device */
+    int32_t threads;         /* threads per workgroup, a multiple of 64 in 64..1024; 0 = 512 */
+} mc_problem;
+
+typedef struct mc_result {
+    double estimate;   /* weighted estimate over the iterations run */
+    double error;      /* its standard deviation */
+    double chi2_dof;   /* chi^2 per degree of freedom (NaN after one iteration) */
+    int32_t iterations;
+    int32_t converged; /* 1 if error <= tau_rel |estimate| after >= 2 iterations */
+    int64_t calls;     /* integrand evaluations: iterations * m * p */
+} mc_result;
+
+/* Optional timing of mc_integrate, measured with HIP events on the call's
+ * stream around each kernel launch. */
+typedef struct mc_timing {
+    double sample_ms;    /* sum over iterations of the sampling kernel */
+    double finalize_ms;  /* sum over iterations of the reduction kernel */
+    int32_t launches;    /* sampling-kernel launches */
+    int32_t blocks;      /* workgroups per sampling launch */
+    int32_t threads;     /* threads per workgroup */
+    int32_t lds_bytes;   /* LDS per workgroup */
+} mc_timing;
+
+/* Human-readable text for a status (static storage). */
+const char *mc_status_string(mc_status status);
+
+/* Sub-cube lattice of Alg. 2: g = the largest integer with g^d <= maxcalls/2
+ * (integer division), m = g^d sub-cubes, p = maxcalls / m samples per
+ * sub-cube.  Host only.  MC_EINVAL for dim outside 1..MC_MAX_DIM, maxcalls < 4
+ * or maxcalls beyond 2^62.  (Problems additionally need g <= 2^30.) */
+mc_status mc_shape(int32_t dim, int64_t maxcalls, int64_t *g, int64_t *m, int64_t *p);
+
+/* Bytes of device workspace the problem needs on the current device.
+ * MC_EINVAL for an invalid problem, MC_EDEVICE if no device is usable. */
+mc_status mc_workspace_bytes(const mc_problem *prob, size_t *bytes);
+
+/* Copies the problem's parameters and tables into the workspace and prepares
+ * it for mc_sample_iteration().  mc_integrate() does this itself. */
+mc_status mc_prepare(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream);
+
+/* One sampling pass, V-Sample (adjust != 0) or V-Sample-No-Adjust (adjust
+ * == 0) of Alg. 3, on a workspace prepared by mc_prepare() for the same
+ * problem.  Synchronous.
+ *   iter       iteration number (part of the random-number counter)
+ *   h_grid     host, dim*(nbins+1) boundaries
+ *   h_out      host, 2 doubles: the iteration estimate I and its variance
+ *   h_hist     host, dim*nbins bin contributions sum I_k^2, or NULL; must be
+ *              NULL when adjust == 0
+ *   d_trace    device or NULL.  When not NULL, the sampling kernel also
+ *              records the sub-cubes t in [t0, t1): first (t1-t0)*p records
+ *              of 3*dim+2 doubles (u_1..u_d, bin_1..bin_d, x_1..x_d, J, f)
+ *              in the order (t, k), then (t1-t0) records of 2 doubles (I_t,
+ *              var_t).  trace_bytes must hold them. */
+mc_status mc_sample_iteration(const mc_problem *prob, uint32_t iter, int32_t adjust,
+                              const double *h_grid, void *d_ws, size_t ws_bytes, void *stream,
+                              double *h_out, double *h_hist, void *d_trace, size_t trace_bytes,
+                              int64_t t0, int64_t t1);
+
+/* Adjust-Bin-Bounds (Alg. 2; Alg. 1 and the text after it): rebuilds the
+ * boundaries so that bins with large contributions become smaller.  Per
+ * axis: three-point smoothing of the contributions, Lepage's damped
+ * compression ((1 - s_i/S) / ln(S/s_i))^alpha, then equal shares of the
+ * compressed weight per new bin.  An axis without positive finite weight is
+ * left unchanged.  Host only; h_grid is updated in place. */
+mc_status mc_refine_grid(int32_t dim, int32_t nbins, double alpha, const double *h_hist,
+                         double *h_grid);
+
+/* Init-Bins (Alg. 2): nbins equal bins per axis.  Host only. */
+mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid);
+
+/* Weighted-Estimates (Alg. 2): inverse-variance weighted mean of k iteration
+ * results, its standard deviation and chi^2 per degree of freedom, written
+ * to h_out[0..2].  Iterations with zero variance, if any, decide the mean
+ * alone.  Host only. */
+mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var, double *h_out);
+
+/* The whole m-Cubes run (Alg. 2): iterations of sampling, weighting, bin
+ * adjustment (first ita iterations) and the convergence check, on the given
+ * stream.  Synchronous.
+ *   h_iters  host, 2*itmax doubles or NULL: per-iteration (I_i, var_i)
+ *   h_grid   host, dim*(nbins+1) doubles or NULL: the final boundaries
+ *   timing   host or NULL */
+mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                       mc_result *out, double *h_iters, double *h_grid, mc_timing *timing);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCUBES_H */

@@ -1,0 +1,280 @@
+"""Python binding of libmcubes (the C ABI in include/mcubes.h).
+
+Argument marshalling only: every step of the sampling pass runs in the HIP
+kernels of libmcubes.so, and the per-iteration host steps run in its C++
+driver.  PyTorch provides the device workspace and the stream.  There is no
+fallback: if the library is missing, loading it raises.
+
+Problems are the dicts produced by ``paper_2202_01753_amd.workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(PKG, "libmcubes.so")
+
+OK, EINVAL, EWORKSPACE, ENONFINITE, EDEVICE = 0, 1, 2, 3, 4
+INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 3}
+EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
+           "mc_sample_iteration", "mc_refine_grid", "mc_init_grid", "mc_weighted_estimate",
+           "mc_integrate")
+
+
+class MCubesError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: status {code} ({status_string(code)})")
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("integrand", C.c_int32),
+        ("dim", C.c_int32),
+        ("params", C.POINTER(C.c_double)),
+        ("n_params", C.c_int64),
+        ("tables", C.POINTER(C.c_double)),
+        ("n_tables", C.c_int64),
+        ("lo", C.POINTER(C.c_double)),
+        ("hi", C.POINTER(C.c_double)),
+        ("maxcalls", C.c_int64),
+        ("nbins", C.c_int32),
+        ("itmax", C.c_int32),
+        ("ita", C.c_int32),
+        ("precision", C.c_int32),
+        ("alpha", C.c_double),
+        ("tau_rel", C.c_double),
+        ("seed", C.c_uint64),
+        ("blocks", C.c_int32),
+        ("threads", C.c_int32),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("error", C.c_double), ("chi2_dof", C.c_double),
+                ("iterations", C.c_int32), ("converged", C.c_int32), ("calls", C.c_int64)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("sample_ms", C.c_double), ("finalize_ms", C.c_double), ("launches", C.c_int32),
+                ("blocks", C.c_int32), ("threads", C.c_int32), ("lds_bytes", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libmcubes.so from the package directory; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime; importing it first makes libmcubes bind
+        # to that same runtime (one HIP runtime per process).
+        import torch  # noqa: F401
+        if not os.path.exists(LIBRARY):
+            raise ImportError(f"{LIBRARY} is not built: run `python -m paper_2202_01753_amd.build`")
+        L = C.CDLL(LIBRARY)
+        dp, vp, sz = C.POINTER(C.c_double), C.c_void_p, C.c_size_t
+        P = C.POINTER(Problem)
+        sig = {
+            "mc_status_string": ([C.c_int32], C.c_char_p),
+            "mc_shape": ([C.c_int32, C.c_int64] + [C.POINTER(C.c_int64)] * 3, C.c_int32),
+            "mc_workspace_bytes": ([P, C.POINTER(C.c_size_t)], C.c_int32),
+            "mc_prepare": ([P, vp, sz, vp], C.c_int32),
+            "mc_sample_iteration": ([P, C.c_uint32, C.c_int32, dp, vp, sz, vp, dp, dp, vp, sz,
+                                     C.c_int64, C.c_int64], C.c_int32),
+            "mc_refine_grid": ([C.c_int32, C.c_int32, C.c_double, dp, dp], C.c_int32),
+            "mc_init_grid": ([C.c_int32, C.c_int32, dp], C.c_int32),
+            "mc_weighted_estimate": ([C.c_int32, dp, dp, dp], C.c_int32),
+            "mc_integrate": ([P, vp, sz, vp, C.POINTER(Result), dp, dp, C.POINTER(Timing)],
+                             C.c_int32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().mc_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise MCubesError(code, what)
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class BoundProblem:
+    """An mc_problem struct plus the host arrays it points into."""
+
+    def __init__(self, prob: dict, blocks: int = 0, threads: int = 0):
+        self.src = prob
+        self.params = _f64(prob["params"])
+        self.tables = _f64(prob.get("tables"))
+        self.lo = _f64(prob["lo"])
+        self.hi = _f64(prob["hi"])
+        self.s = Problem(
+            integrand=INTEGRANDS[prob["integrand"]], dim=int(prob["dim"]), params=_dp(self.params),
+            n_params=len(self.params), tables=_dp(self.tables),
+            n_tables=0 if self.tables is None else len(self.tables), lo=_dp(self.lo),
+            hi=_dp(self.hi), maxcalls=int(prob["maxcalls"]), nbins=int(prob["nbins"]),
+            itmax=int(prob["itmax"]), ita=int(prob.get("ita", prob["itmax"])), precision=0,
+            alpha=float(prob["alpha"]), tau_rel=float(prob.get("tau_rel", 0.0)),
+            seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads))
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def shape(dim: int, maxcalls: int):
+    g, m, p = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().mc_shape(dim, maxcalls, C.byref(g), C.byref(m), C.byref(p)), "mc_shape")
+    return g.value, m.value, p.value
+
+
+def workspace_bytes(bp: BoundProblem) -> int:
+    n = C.c_size_t()
+    _check(lib().mc_workspace_bytes(bp.ref, C.byref(n)), "mc_workspace_bytes")
+    return n.value
+
+
+def refine_grid(dim: int, nbins: int, alpha: float, hist, grid):
+    out = _f64(grid).copy()
+    h = _f64(hist)
+    _check(lib().mc_refine_grid(dim, nbins, alpha, _dp(h), _dp(out)), "mc_refine_grid")
+    return out
+
+
+def init_grid(dim: int, nbins: int):
+    g = np.zeros(dim * (nbins + 1))
+    _check(lib().mc_init_grid(dim, nbins, _dp(g)), "mc_init_grid")
+    return g
+
+
+def weighted_estimate(I, var):
+    I, var = _f64(I), _f64(var)
+    out = np.zeros(3)
+    _check(lib().mc_weighted_estimate(len(I), _dp(I), _dp(var), _dp(out)), "mc_weighted_estimate")
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+# ---------------------------------------------------------------- device-side calls (torch)
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the m-Cubes sampling kernels need an MI355X")
+    return torch
+
+
+class Workspace:
+    """Device workspace (a torch uint8 tensor) sized for one problem."""
+
+    def __init__(self, bp: BoundProblem, device="cuda"):
+        torch = _torch()
+        self.nbytes = workspace_bytes(bp)
+        self.tensor = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.tensor.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class IntegrationResult:
+    estimate: float
+    error: float
+    chi2_dof: float
+    iterations: int
+    converged: bool
+    calls: int
+    it_I: np.ndarray
+    it_var: np.ndarray
+    grid: np.ndarray
+    sample_ms: float = 0.0
+    finalize_ms: float = 0.0
+    blocks: int = 0
+    threads: int = 0
+    lds_bytes: int = 0
+
+
+def integrate(prob: dict, ws: Workspace | None = None, stream=None, blocks: int = 0,
+              threads: int = 0, timing: bool = False, bp: BoundProblem | None = None):
+    bp = bp or BoundProblem(prob, blocks, threads)
+    ws = ws or Workspace(bp)
+    d, nb, itmax = int(prob["dim"]), int(prob["nbins"]), int(prob["itmax"])
+    res = Result()
+    iters = np.zeros(2 * itmax)
+    grid = np.zeros(d * (nb + 1))
+    tm = Timing() if timing else None
+    _check(lib().mc_integrate(bp.ref, ws.ptr, ws.nbytes, _stream(stream), C.byref(res), _dp(iters),
+                              _dp(grid), C.byref(tm) if tm is not None else None), "mc_integrate")
+    k = res.iterations
+    out = IntegrationResult(res.estimate, res.error, res.chi2_dof, k, bool(res.converged),
+                            res.calls, iters[0:2 * k:2].copy(), iters[1:2 * k:2].copy(), grid)
+    if tm is not None:
+        out.sample_ms, out.finalize_ms = tm.sample_ms, tm.finalize_ms
+        out.blocks, out.threads, out.lds_bytes = tm.blocks, tm.threads, tm.lds_bytes
+    return out
+
+
+class Sampler:
+    """Step-level access: one prepared workspace, one sampling pass per call."""
+
+    def __init__(self, prob: dict, blocks: int = 0, threads: int = 0, stream=None):
+        self.prob = prob
+        self.bp = BoundProblem(prob, blocks, threads)
+        self.ws = Workspace(self.bp)
+        self.stream = stream
+        self.d, self.nb = int(prob["dim"]), int(prob["nbins"])
+        self.g, self.m, self.p = shape(self.d, int(prob["maxcalls"]))
+        _check(lib().mc_prepare(self.bp.ref, self.ws.ptr, self.ws.nbytes, _stream(stream)),
+               "mc_prepare")
+
+    def sample(self, it: int, grid, adjust: bool = True, trace_range=None):
+        """Returns dict(I, var, hist, strace, ctrace) like the oracle's vsample."""
+        torch = _torch()
+        grid = _f64(grid)
+        out = np.zeros(2)
+        hist = np.zeros(self.d * self.nb) if adjust else None
+        tr, t0, t1, nbytes = None, 0, 0, 0
+        if trace_range is not None:
+            t0, t1 = trace_range
+            rec = 3 * self.d + 2
+            n = (t1 - t0) * self.p * rec + 2 * (t1 - t0)
+            tr = torch.full((max(n, 1),), float("nan"), dtype=torch.float64, device=self.ws.tensor.device)
+            nbytes = n * 8
+        code = lib().mc_sample_iteration(
+            self.bp.ref, it, 1 if adjust else 0, _dp(grid), self.ws.ptr, self.ws.nbytes,
+            _stream(self.stream), _dp(out), _dp(hist),
+            C.c_void_p(tr.data_ptr()) if tr is not None else None, nbytes, t0, t1)
+        res = {"I": float(out[0]), "var": float(out[1]), "hist": hist, "strace": None,
+               "ctrace": None, "status": code}
+        if code not in (OK, ENONFINITE):
+            _check(code, "mc_sample_iteration")
+        if tr is not None and code == OK:
+            a = tr.cpu().numpy()
+            ns = (t1 - t0) * self.p
+            res["strace"] = a[:ns * rec].reshape(ns, rec)
+            res["ctrace"] = a[ns * rec:ns * rec + 2 * (t1 - t0)].reshape(t1 - t0, 2)
+        return res

@@ -1,0 +1,245 @@
+"""GPU parity: the HIP sampling path (through the C ABI) against the CPU oracle.
+
+Bars (FP64 path):
+  * sample points are bit-exact: uniforms, bin indices, points x and Jacobians J;
+  * f is bit-exact for integrands built from basic IEEE operations (constant,
+    corner peak); the exponential-based ones differ only by the libm/ocml exp
+    rounding (a few ulp);
+  * per-iteration estimate and variance agree within 1e-12 relative (the
+    estimate relative to sum |I_t|), bin contributions within 1e-12 relative;
+  * the grid refined from the GPU's histogram is identical bit for bit in the
+    library and in the oracle (lockstep)."""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+import oracle as O
+from paper_2202_01753_amd import mcubes as M
+from paper_2202_01753_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _ulps(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    ia = a.view(np.int64)
+    ib = b.view(np.int64)
+    ia = np.where(ia < 0, np.int64(-2**63) - ia, ia)
+    ib = np.where(ib < 0, np.int64(-2**63) - ib, ib)
+    return np.abs(ia - ib)
+
+
+def _exact_f(prob):
+    return prob["integrand"] in ("const", "corner_peak")
+
+
+def _compare_records(prob, gpu, ref, label=""):
+    d = prob["dim"]
+    G, R = gpu["strace"], ref["strace"]
+    assert G.shape == R.shape, label
+    assert np.array_equal(G[:, :d], R[:, :d]), f"{label}: uniforms differ"
+    assert np.array_equal(G[:, d:2 * d], R[:, d:2 * d]), f"{label}: bins differ"
+    assert np.array_equal(G[:, 2 * d:3 * d], R[:, 2 * d:3 * d]), f"{label}: points differ"
+    assert np.array_equal(G[:, 3 * d], R[:, 3 * d]), f"{label}: Jacobians differ"
+    if _exact_f(prob):
+        assert np.array_equal(G[:, 3 * d + 1], R[:, 3 * d + 1]), f"{label}: f differs"
+    else:
+        # exp rounding (ocml vs glibc, each within a couple of ulp in the far tail)
+        # followed by up to two products with the table values
+        assert _ulps(G[:, 3 * d + 1], R[:, 3 * d + 1]).max() <= 8, f"{label}: f beyond 8 ulp"
+    gc, rc = gpu["ctrace"], ref["ctrace"]
+    scale = np.abs(rc[:, 0]).sum()
+    if _exact_f(prob):
+        assert np.array_equal(gc, rc), f"{label}: per-cube values differ"
+    else:
+        assert np.all(np.abs(gc[:, 0] - rc[:, 0]) <= 1e-14 * np.abs(rc[:, 0]) + 1e-300)
+        assert np.all(np.abs(gc[:, 1] - rc[:, 1]) <= 1e-12 * np.abs(rc[:, 1]) + 1e-14 * rc[:, 0] ** 2)
+    return scale
+
+
+def _compare_totals(gpu, ref, scale, label=""):
+    assert abs(gpu["I"] - ref["I"]) <= TOL * scale, f"{label}: I {gpu['I']} vs {ref['I']}"
+    assert abs(gpu["var"] - ref["var"]) <= TOL * abs(ref["var"]) + 1e-300, \
+        f"{label}: var {gpu['var']} vs {ref['var']}"
+    if ref["hist"] is not None:
+        h, r = gpu["hist"], ref["hist"]
+        assert np.all(np.abs(h - r) <= TOL * np.abs(r) + 1e-300), f"{label}: histogram"
+
+
+def _lockstep(prob, iters=None, threads=0, blocks=0):
+    d, nb = prob["dim"], prob["nbins"]
+    s = M.Sampler(prob, blocks=blocks, threads=threads)
+    grid = O.init_grid(d, nb)
+    iters = prob["itmax"] if iters is None else iters
+    for it in range(iters):
+        adjust = it < prob["ita"]
+        gpu = s.sample(it, grid, adjust, trace_range=(0, s.m))
+        ref = O.vsample(prob, it, grid, hist=adjust, trace=True)
+        scale = _compare_records(prob, gpu, ref, f"iter {it}")
+        _compare_totals(gpu, ref, scale, f"iter {it}")
+        if adjust:
+            a = M.refine_grid(d, nb, prob["alpha"], gpu["hist"], grid)
+            b = O.refine(d, nb, prob["alpha"], gpu["hist"], grid)
+            assert np.array_equal(a, b), f"iter {it}: refined grids differ"
+            grid = a
+    return grid
+
+
+# ---------------------------------------------------------------- lockstep, tiny runs
+
+def test_lockstep_small_gaussian_config():
+    _lockstep(W.config_small(seed=11))
+
+
+def test_lockstep_corner_peak_bit_exact():
+    _lockstep(W.corner_peak(3, 5, maxcalls=5000, nbins=40, itmax=4, seed=2**40 + 3))
+
+
+def test_lockstep_tables_d6():
+    _lockstep(W.config_tables(seed=7, maxcalls=30_000, itmax=3))
+
+
+def test_lockstep_constant_exact():
+    prob = W.const(2, 2.5, maxcalls=8192, nbins=128, itmax=2, lo=np.array([0.0, -1.0]),
+                   hi=np.array([1.0, 3.0]), seed=9)
+    s = M.Sampler(prob)
+    r = s.sample(0, O.init_grid(2, 128), adjust=False)
+    assert r["I"] == 10.0 and r["var"] == 0.0
+
+
+@pytest.mark.parametrize("case", [
+    dict(make=lambda: W.gauss_product(1, 3, maxcalls=4, nbins=2, itmax=3, seed=1), name="d1 m2"),
+    dict(make=lambda: W.corner_peak(3, 4, maxcalls=1000, nbins=2, itmax=3, seed=5), name="ragged nb2"),
+    dict(make=lambda: W.corner_peak(10, 6, maxcalls=10_000, nbins=64, itmax=3, seed=6), name="p9"),
+    dict(make=lambda: W.corner_peak(16, 7, maxcalls=2**17, nbins=16, itmax=2, seed=8), name="d16"),
+    dict(make=lambda: W.gauss_product(2, 9, maxcalls=20_000, nbins=4000, itmax=2, seed=4), name="nb4000"),
+    dict(make=lambda: W.gauss_product(3, 10, maxcalls=6000, nbins=30, itmax=4, ita=2, seed=3,
+                                      lo=np.array([-1.0, 0.5, 2.0]), hi=np.array([1.0, 0.75, 9.0])),
+         name="bounds no-adjust"),
+], ids=lambda c: c["name"])
+def test_lockstep_edge_cases(case):
+    _lockstep(case["make"]())
+
+
+@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 7), (256, 0), (1024, 0), (512, 3)])
+def test_launch_shape_does_not_change_samples(threads, blocks):
+    prob = W.corner_peak(4, 12, maxcalls=40_000, nbins=50, itmax=2, seed=77)
+    _lockstep(prob, threads=threads, blocks=blocks)
+
+
+# ---------------------------------------------------------------- whole runs
+
+def test_integrate_matches_oracle_free_running():
+    prob = W.config_small(seed=21)
+    g = M.integrate(prob)
+    o = O.integrate(prob)
+    assert g.iterations == o["iterations"] == 10
+    assert np.allclose(g.it_I, o["it_I"], rtol=1e-11, atol=0)
+    assert np.allclose(g.it_var, o["it_var"], rtol=1e-10, atol=0)
+    assert g.estimate == pytest.approx(o["estimate"], rel=1e-11)
+    assert g.error == pytest.approx(o["error"], rel=1e-10)
+    assert g.chi2_dof == pytest.approx(o["chi2_dof"], rel=1e-8)
+    exact = CF.exact(prob)
+    assert abs(g.estimate - exact) < 5 * g.error
+
+
+def test_integrate_corner_peak_free_running_and_convergence():
+    prob = W.corner_peak(5, 14, maxcalls=200_000, nbins=100, itmax=12, tau_rel=1e-3, seed=5)
+    g = M.integrate(prob)
+    o = O.integrate(prob)
+    assert g.iterations == o["iterations"] and g.converged == o["converged"]
+    assert g.converged and g.error <= 1e-3 * abs(g.estimate)
+    assert np.allclose(g.it_I, o["it_I"], rtol=1e-11, atol=0)
+    assert g.estimate == pytest.approx(o["estimate"], rel=1e-11)
+    assert abs(g.estimate - CF.exact(prob)) < 5 * g.error
+
+
+def test_deterministic_repeat():
+    prob = W.config_tables(seed=3, maxcalls=2_000_000, itmax=1)
+    s = M.Sampler(prob)
+    grid = O.init_grid(6, 500)
+    a = s.sample(0, grid)
+    b = s.sample(0, grid)
+    assert a["I"] == b["I"] and a["var"] == b["var"]
+    assert np.allclose(a["hist"], b["hist"], rtol=TOL, atol=0)
+
+
+# ---------------------------------------------------------------- full-size configurations
+
+def _sampled_full_size(prob, windows, n=1500):
+    s = M.Sampler(prob)
+    d, nb = prob["dim"], prob["nbins"]
+    rng = np.random.default_rng(1)
+    grid = np.concatenate([np.concatenate([[0.0], np.sort(rng.random(nb - 1)), [1.0]])
+                           for _ in range(d)])
+    full = None
+    for frac in windows:
+        t0 = min(int(frac * s.m), s.m - n)
+        gpu = s.sample(1, grid, True, trace_range=(t0, t0 + n))
+        ref = O.vsample(prob, 1, grid, t0=t0, t1=t0 + n, hist=False, trace=True)
+        _compare_records(prob, gpu, ref, f"cubes [{t0}, {t0 + n})")
+        full = gpu
+    # properties of the whole pass: each axis row of the histogram sums to the
+    # same total (every sample adds I_k^2 once per axis)
+    rows = full["hist"].reshape(d, nb).sum(axis=1)
+    assert np.allclose(rows, rows[0], rtol=1e-12)
+    assert full["var"] > 0 and full["I"] > 0
+    return s, full
+
+
+def test_full_size_tables_1e8():
+    prob = W.config_tables(seed=1)
+    s, full = _sampled_full_size(prob, [0.0, 0.37, 1.0])
+    # on the uniform grid the pass is an unbiased estimate of the closed form
+    r = s.sample(0, O.init_grid(6, 500), adjust=False)
+    exact = CF.exact(prob)
+    assert abs(r["I"] - exact) < 5 * math.sqrt(r["var"])
+
+
+def test_full_size_corner8_1e9():
+    prob = W.config_corner8(seed=1)
+    s, full = _sampled_full_size(prob, [0.0, 0.5, 1.0], n=800)
+    r = s.sample(0, O.init_grid(8, 500), adjust=True)
+    exact = CF.exact(prob)
+    assert abs(r["I"] - exact) < 5 * math.sqrt(r["var"])
+
+
+def test_counter_high_word():
+    """More than 2^32 sub-cubes: the high word of the cube index enters the counter."""
+    prob = W.gauss_product(2, 2, maxcalls=2**34, nbins=64, itmax=1, seed=3)
+    s = M.Sampler(prob)
+    assert s.m > 2**32
+    grid = O.init_grid(2, 64)
+    t0 = s.m - 1000
+    gpu = s.sample(0, grid, False, trace_range=(t0, s.m))
+    ref = O.vsample(prob, 0, grid, t0=t0, t1=s.m, hist=False, trace=True)
+    _compare_records(prob, gpu, ref, "t >= 2^32")
+
+
+# ---------------------------------------------------------------- error paths through the C ABI
+
+def test_error_paths():
+    import ctypes as C
+    import torch
+    prob = W.config_small()
+    bp = M.BoundProblem(prob)
+    need = M.workspace_bytes(bp)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    res = M.Result(estimate=-1.0)
+    code = M.lib().mc_integrate(bp.ref, C.c_void_p(ws.data_ptr()), need - 1, None, C.byref(res),
+                                None, None, None)
+    assert code == M.EWORKSPACE and res.estimate == -1.0
+    inf = W.const(2, np.inf, maxcalls=1000, nbins=10, itmax=2)
+    with pytest.raises(M.MCubesError) as e:
+        M.integrate(inf)
+    assert e.value.code == M.ENONFINITE
+    # a non-finite pass does not poison the next one on the same workspace
+    s = M.Sampler(W.const(2, 1.0, maxcalls=8192, nbins=128, itmax=1))
+    assert s.sample(0, O.init_grid(2, 128))["status"] == M.OK
+    with pytest.raises(M.MCubesError) as e:
+        s.sample(0, O.init_grid(2, 128), adjust=False, trace_range=(0, s.m + 1))
+    assert e.value.code == M.EINVAL
