@@ -11,7 +11,7 @@ samples per second over the K timed steps (iterations * m * p per step).
 The roofline entry is for the sampling kernel: its average launch duration
 comes from HIP events recorded by the library on the launch stream, and its
 algorithmic work is the per-sample VALU lane-operation count of the method's
-steps (quarter-rate operations weighted 4), times the samples per launch,
+steps (one issue slot per full-rate instruction), times the samples per launch,
 against the chip's VALU issue rate.  The CPU baseline times the FP64 oracle on
 one host core over a bounded block of sub-cubes of the same workload.
 """
@@ -27,27 +27,37 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = VALU lane-op issue rate.
+# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = VALU lane-op issue rate
+# (a wave64 full-rate VALU instruction occupies a SIMD for 4 clocks).
 CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
 VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 lane-ops/s
 
 
 def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
-    """Algorithmic VALU lane-operations per sample (quarter-rate ops count 4).
+    """Algorithmic VALU lane-operations per sample of the FP64 path.
 
-    Per sample: ceil(d/2) Philox4x32-10 blocks (19 vector 32x32->64 products
-    at 4 + 39 XOR), per axis 20 (uniform 5, stratified coordinate 2, bin index
-    and clamp 7, boundary address and width 2, point 2, Jacobian 2), the
-    integrand, 3 for f*J/(mp) and the finiteness check, 3 (p-1)/p for the
-    shifted sums, 1 + d for the bin-contribution addresses when adjusting, and
-    per sub-cube (18 + 5d)/p for the variance, two compensated additions and
-    the digit odometer.  Integrands: Gaussian 3d + 20 (exp), corner peak
-    d + popcount-powering + 10 (division), tables = Gaussian + 2 x 21 + 2.
+    Counted from the method's steps at one issue slot per full-rate VALU
+    instruction (measured on gfx950: 32x32->64 integer products, FP64 add/mul/
+    fma and conversions all issue at the full rate; v_rcp_f64 counts 4), with
+    work that is uniform across the wavefront or invariant across a sub-cube's
+    samples excluded:
+      Philox4x32-10 block       17 products + 34 XOR          (ceil(d/2) blocks)
+      per axis                  uniform 5, stratified coordinate 2, bin index
+                                and clamp 7, boundary address and width 2,
+                                point 2, Jacobian 2           = 20
+      Gaussian product          3 per axis + exp 20
+      corner peak               d fma + binary powering + division 13
+      two bilinear tables       2 x 21 + 2 products (on top of the Gaussian)
+      f J / (m p), finiteness   4
+      shifted sums              3 (p-1)/p
+      bin contributions         1 + d addresses (adjusting iterations)
+      per sub-cube, / p         variance 5, two compensated additions 14,
+                                digit odometer 4 d, digit conversion d
     """
     d = int(prob["dim"])
     _, _, p = g_m_p
     kind = prob["integrand"]
-    philox = math.ceil(d / 2) * (19 * 4 + 39)
+    philox = math.ceil(d / 2) * (17 + 34)
     per_axis = 20 * d
     if kind == "const":
         f = 0
@@ -55,10 +65,10 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
         f = 3 * d + 20
     elif kind == "corner_peak":
         e = d + 1
-        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + 10
+        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + 13
     else:
         f = 3 * d + 20 + 2 * 21 + 2
-    tail = 3 + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (18 + 5 * d) / p
+    tail = 4 + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (19 + 5 * d) / p
     return float(philox + per_axis + f + tail)
 
 
@@ -100,7 +110,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = 256 * 1024 * 1024
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_each_way": nbytes, "dispatches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)

@@ -34,16 +34,17 @@ struct SampleArgs {
     double pd;              // p
     double inv_pm1;         // 1 / (p - 1)
     double cval;            // constant integrand value
-    double lo[kMaxDim];
-    double span[kMaxDim];   // hi - lo
-    double q[kMaxDim];      // nb * span
-    double pa[kMaxDim];     // gaussian centres or corner-peak coefficients
-    double pb[kMaxDim];     // gaussian inverse widths
+    const double *consts;   // kConstStride doubles per axis, see below
     int32_t sdig[kMaxDim];  // stride in base g, least significant digit first
 };
 
-// Returns the sampling kernel for (integrand, dim), or nullptr.
-const void *sample_kernel(int integrand, int dim);
+// Per-axis constants, copied to LDS by every workgroup:
+//   [0] lo   [1] span = hi - lo   [2] q = nb * span
+//   [3] Gaussian centre or corner-peak coefficient   [4] Gaussian 1/width   [5] 0
+constexpr int kConstStride = 6;
+
+// Returns the sampling kernel for (integrand, dim) and its tracing variant, or nullptr.
+const void *sample_kernel(int integrand, int dim, bool trace);
 
 // Launches the sampling kernel; lds_bytes is the dynamic LDS size.
 hipError_t launch_sample(int integrand, int dim, int blocks, int threads, size_t lds_bytes,

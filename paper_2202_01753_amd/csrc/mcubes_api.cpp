@@ -76,7 +76,7 @@ int expected_params(int integrand, int d) {
 int threads_of(const mc_problem *pr) { return pr->threads ? pr->threads : kDefaultThreads; }
 
 size_t lds_bytes_of(int d, int nb, bool hist) {
-    return (size_t)d * (nb + 1) * sizeof(double) + (hist ? (size_t)d * nb * sizeof(double) : 0);
+    return sizeof(double) * ((size_t)kConstStride * d + (size_t)d * (nb + 1) + (hist ? (size_t)d * nb : 0));
 }
 
 mc_status validate(const mc_problem *pr) {
@@ -116,7 +116,7 @@ struct Geometry {
     int blocks_adj, blocks_noadj;
     size_t lds_adj, lds_noadj;
     int hist_stride;          // doubles per workgroup histogram (padded)
-    size_t off_grid, off_tables, off_partials, off_out, off_flag, total;
+    size_t off_consts, off_grid, off_tables, off_partials, off_out, off_flag, total;
 };
 
 std::mutex g_attr_mu;
@@ -156,7 +156,7 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     G.threads = threads_of(pr);
     G.lds_adj = lds_bytes_of(d, nb, true);
     G.lds_noadj = lds_bytes_of(d, nb, false);
-    const void *fn = sample_kernel(pr->integrand, d);
+    const void *fn = sample_kernel(pr->integrand, d, false);
     if (!fn) return MC_EINVAL;
     st = blocks_for(fn, G.threads, G.lds_adj, G.m, pr->blocks, &G.blocks_adj);
     if (st != MC_OK) return st;
@@ -166,6 +166,8 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     const size_t part_adj = (4 + (size_t)G.hist_stride) * G.blocks_adj;
     const size_t part_noadj = 4 * (size_t)G.blocks_noadj;
     size_t off = 0;
+    G.off_consts = off;
+    off = align_up(off + sizeof(double) * kConstStride * d);
     G.off_grid = off;
     off = align_up(off + sizeof(double) * d * (nb + 1));
     G.off_tables = off;
@@ -183,11 +185,6 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
 
 // ------------------------------------------------------------------ one sampling pass
 
-struct Pass {
-    double I, var;
-    bool nonfinite;
-};
-
 void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter, bool adjust,
                int blocks, SampleArgs *a) {
     std::memset(a, 0, sizeof(*a));
@@ -197,6 +194,7 @@ void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter,
                                                    : nullptr;
     a->partials = reinterpret_cast<double *>(ws + G.off_partials);
     a->flag = reinterpret_cast<uint32_t *>(ws + G.off_flag);
+    a->consts = reinterpret_cast<const double *>(ws + G.off_consts);
     a->trace = nullptr;
     a->m = G.m;
     a->stride = (int64_t)blocks * G.threads;
@@ -211,26 +209,7 @@ void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter,
     a->inv = 1.0 / (double)(G.m * G.p);
     a->pd = (double)G.p;
     a->inv_pm1 = 1.0 / (a->pd - 1.0);
-    for (int j = 0; j < d; ++j) {
-        a->lo[j] = pr->lo[j];
-        a->span[j] = pr->hi[j] - pr->lo[j];
-        a->q[j] = (double)nb * a->span[j];
-    }
-    switch (pr->integrand) {
-    case MC_F_CONST:
-        a->cval = pr->params[0];
-        break;
-    case MC_F_GAUSS_PRODUCT:
-    case MC_F_GAUSS_TABLES:
-        for (int j = 0; j < d; ++j) {
-            a->pa[j] = pr->params[j];
-            a->pb[j] = 1.0 / pr->params[d + j];
-        }
-        break;
-    case MC_F_CORNER_PEAK:
-        for (int j = 0; j < d; ++j) a->pa[j] = pr->params[j];
-        break;
-    }
+    if (pr->integrand == MC_F_CONST) a->cval = pr->params[0];
     // the per-lane stride in base g (only d digits are used: a lane that
     // overflows the top digit has left the lattice)
     int64_t rest = a->stride;
@@ -274,7 +253,7 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     HIP_TRY(hipMemcpyAsync(ws + G.off_grid, h_grid, sizeof(double) * d * (nb + 1),
                            hipMemcpyHostToDevice, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[0], stream));
-    HIP_TRY(allow_lds(sample_kernel(pr->integrand, d), lds));
+    HIP_TRY(allow_lds(sample_kernel(pr->integrand, d, trace != nullptr), lds));
     HIP_TRY(launch_sample(pr->integrand, d, blocks, G.threads, lds, stream, a));
     if (ev) HIP_TRY(hipEventRecord(ev->e[1], stream));
     double *out_dev = reinterpret_cast<double *>(ws + G.off_out);
@@ -294,7 +273,33 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     return out_host[2] != 0.0 ? MC_ENONFINITE : MC_OK;
 }
 
+// Per-axis constants in the layout the sampling kernel keeps in LDS.
+std::vector<double> axis_constants(const mc_problem *pr) {
+    const int d = pr->dim, nb = pr->nbins;
+    std::vector<double> c((size_t)kConstStride * d, 0.0);
+    for (int j = 0; j < d; ++j) {
+        double *cj = c.data() + (size_t)kConstStride * j;
+        cj[0] = pr->lo[j];
+        cj[1] = pr->hi[j] - pr->lo[j];
+        cj[2] = (double)nb * cj[1];
+        switch (pr->integrand) {
+        case MC_F_GAUSS_PRODUCT:
+        case MC_F_GAUSS_TABLES:
+            cj[3] = pr->params[j];
+            cj[4] = 1.0 / pr->params[d + j];
+            break;
+        case MC_F_CORNER_PEAK:
+            cj[3] = pr->params[j];
+            break;
+        }
+    }
+    return c;
+}
+
 mc_status prepare(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t stream) {
+    const std::vector<double> consts = axis_constants(pr);
+    HIP_TRY(hipMemcpyAsync(ws + G.off_consts, consts.data(), sizeof(double) * consts.size(),
+                           hipMemcpyHostToDevice, stream));
     if (pr->integrand == MC_F_GAUSS_TABLES)
         HIP_TRY(hipMemcpyAsync(ws + G.off_tables, pr->tables, sizeof(double) * kTablesLen,
                                hipMemcpyHostToDevice, stream));

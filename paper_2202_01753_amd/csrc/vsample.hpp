@@ -73,11 +73,11 @@ __device__ __forceinline__ double bilinear(const double *__restrict__ T, double 
 }
 
 template <int D>
-__device__ __forceinline__ double gauss_product(const SampleArgs &a, const double (&x)[D]) {
+__device__ __forceinline__ double gauss_product(const double *sC, const double (&x)[D]) {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const double t = (x[j] - a.pa[j]) * a.pb[j];
+        const double t = (x[j] - sC[kConstStride * j + 3]) * sC[kConstStride * j + 4];
         acc = __fma_rn(t, t, acc);
     }
     return exp(-acc);
@@ -85,10 +85,10 @@ __device__ __forceinline__ double gauss_product(const SampleArgs &a, const doubl
 
 // S^(D+1) by left-to-right binary powering, then one correctly rounded division.
 template <int D>
-__device__ __forceinline__ double corner_peak(const SampleArgs &a, const double (&x)[D]) {
+__device__ __forceinline__ double corner_peak(const double *sC, const double (&x)[D]) {
     double S = 1.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) S = __fma_rn(a.pa[j], x[j], S);
+    for (int j = 0; j < D; ++j) S = __fma_rn(sC[kConstStride * j + 3], x[j], S);
     constexpr unsigned e = (unsigned)(D + 1);
     constexpr int top = 31 - __builtin_clz(e);
     double pw = S;
@@ -101,16 +101,17 @@ __device__ __forceinline__ double corner_peak(const SampleArgs &a, const double 
 }
 
 template <int F, int D>
-__device__ __forceinline__ double integrand(const SampleArgs &a, const double (&x)[D]) {
+__device__ __forceinline__ double integrand(const SampleArgs &a, const double *sC,
+                                            const double (&x)[D]) {
     if constexpr (F == 0) {
         return a.cval;
     } else if constexpr (F == 1) {
-        return gauss_product<D>(a, x);
+        return gauss_product<D>(sC, x);
     } else if constexpr (F == 2) {
-        return corner_peak<D>(a, x);
+        return corner_peak<D>(sC, x);
     } else {
         static_assert(D >= 4, "table integrand needs four axes");
-        const double G = gauss_product<D>(a, x);
+        const double G = gauss_product<D>(sC, x);
         const double T1 = bilinear(a.tables, x[0], x[1]);
         const double T2 = bilinear(a.tables + kTableN * kTableN, x[2], x[3]);
         return (G * T1) * T2;
@@ -138,7 +139,9 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
 
 // ---------------------------------------------------------------- the kernel
 
-template <int F, int D>
+// TRACE instantiations additionally write per-sample and per-cube records for
+// the sub-cubes [t0, t1); everything else is the same code.
+template <int F, int D, bool TRACE>
 __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) {
     extern __shared__ double lds[];
     __shared__ double wave_tot[kMaxBlock / 64][4];
@@ -146,11 +149,13 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
 
     const int nb = a.nb;
     const int row = nb + 1;
-    double *sB = lds;                 // D rows of nb+1 boundaries
-    double *sH = lds + D * row;       // D rows of nb bin contributions
+    double *sC = lds;                       // D blocks of per-axis constants
+    double *sB = lds + kConstStride * D;    // D rows of nb+1 boundaries
+    double *sH = sB + D * row;              // D rows of nb bin contributions
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
 
+    for (int i = tid; i < kConstStride * D; i += nthr) sC[i] = a.consts[i];
     for (int i = tid; i < D * row; i += nthr) sB[i] = a.grid[i];
     if (a.hist)
         for (int i = tid; i < D * nb; i += nthr) sH[i] = 0.0;
@@ -181,7 +186,7 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
 #pragma unroll
         for (int j = 0; j < D; ++j) cd[j] = (double)dig[j];
         const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        const bool traced = a.trace != nullptr && (int64_t)t >= a.t0 && (int64_t)t < a.t1;
+        const bool traced = TRACE && (int64_t)t >= a.t0 && (int64_t)t < a.t1;
 
         double I0 = 0.0, S1 = 0.0, S2 = 0.0;
         for (int k = 0; k < a.p; ++k) {
@@ -213,8 +218,9 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
                 const double left = B[0];
                 const double width = B[1] - left;
                 const double xu = __fma_rn(frac, width, left);
-                x[j] = __fma_rn(a.span[j], xu, a.lo[j]);
-                J = J * (width * a.q[j]);
+                const double *cj = sC + kConstStride * j;
+                x[j] = __fma_rn(cj[1], xu, cj[0]);
+                J = J * (width * cj[2]);
                 bin[j] = i;
                 if (traced) {
                     double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
@@ -223,7 +229,7 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
                     r[2 * D + j] = x[j];
                 }
             }
-            const double f = integrand<F, D>(a, x);
+            const double f = integrand<F, D>(a, sC, x);
             bad |= !isfinite(f);
             const double Fv = f * J;
             const double Ik = Fv * a.inv;
@@ -308,7 +314,12 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
 template <int F, int D>
 hipError_t launch_sample_fd(int blocks, int threads, size_t lds_bytes, hipStream_t stream,
                             const SampleArgs &args) {
-    hipLaunchKernelGGL((vsample_kernel<F, D>), dim3(blocks), dim3(threads), lds_bytes, stream, args);
+    if (args.trace)
+        hipLaunchKernelGGL((vsample_kernel<F, D, true>), dim3(blocks), dim3(threads), lds_bytes,
+                           stream, args);
+    else
+        hipLaunchKernelGGL((vsample_kernel<F, D, false>), dim3(blocks), dim3(threads), lds_bytes,
+                           stream, args);
     return hipGetLastError();
 }
 

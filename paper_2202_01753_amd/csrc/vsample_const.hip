@@ -26,24 +26,40 @@ hipError_t launch_sample_f0(int dim, int blocks, int threads, size_t lds_bytes,
     }
 }
 
-const void *sample_kernel_f0(int dim) {
+const void *sample_kernel_f0(int dim, bool trace) {
     switch (dim) {
-    case 1: return reinterpret_cast<const void *>(&vsample_kernel<0, 1>);
-    case 2: return reinterpret_cast<const void *>(&vsample_kernel<0, 2>);
-    case 3: return reinterpret_cast<const void *>(&vsample_kernel<0, 3>);
-    case 4: return reinterpret_cast<const void *>(&vsample_kernel<0, 4>);
-    case 5: return reinterpret_cast<const void *>(&vsample_kernel<0, 5>);
-    case 6: return reinterpret_cast<const void *>(&vsample_kernel<0, 6>);
-    case 7: return reinterpret_cast<const void *>(&vsample_kernel<0, 7>);
-    case 8: return reinterpret_cast<const void *>(&vsample_kernel<0, 8>);
-    case 9: return reinterpret_cast<const void *>(&vsample_kernel<0, 9>);
-    case 10: return reinterpret_cast<const void *>(&vsample_kernel<0, 10>);
-    case 11: return reinterpret_cast<const void *>(&vsample_kernel<0, 11>);
-    case 12: return reinterpret_cast<const void *>(&vsample_kernel<0, 12>);
-    case 13: return reinterpret_cast<const void *>(&vsample_kernel<0, 13>);
-    case 14: return reinterpret_cast<const void *>(&vsample_kernel<0, 14>);
-    case 15: return reinterpret_cast<const void *>(&vsample_kernel<0, 15>);
-    case 16: return reinterpret_cast<const void *>(&vsample_kernel<0, 16>);
+    case 1: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 1, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 1, false>);
+    case 2: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 2, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 2, false>);
+    case 3: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 3, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 3, false>);
+    case 4: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 4, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 4, false>);
+    case 5: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 5, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 5, false>);
+    case 6: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 6, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 6, false>);
+    case 7: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 7, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 7, false>);
+    case 8: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 8, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 8, false>);
+    case 9: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 9, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 9, false>);
+    case 10: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 10, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 10, false>);
+    case 11: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 11, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 11, false>);
+    case 12: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 12, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 12, false>);
+    case 13: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 13, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 13, false>);
+    case 14: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 14, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 14, false>);
+    case 15: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 15, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 15, false>);
+    case 16: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 16, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<0, 16, false>);
     default: return nullptr;
     }
 }

@@ -26,24 +26,40 @@ hipError_t launch_sample_f1(int dim, int blocks, int threads, size_t lds_bytes,
     }
 }
 
-const void *sample_kernel_f1(int dim) {
+const void *sample_kernel_f1(int dim, bool trace) {
     switch (dim) {
-    case 1: return reinterpret_cast<const void *>(&vsample_kernel<1, 1>);
-    case 2: return reinterpret_cast<const void *>(&vsample_kernel<1, 2>);
-    case 3: return reinterpret_cast<const void *>(&vsample_kernel<1, 3>);
-    case 4: return reinterpret_cast<const void *>(&vsample_kernel<1, 4>);
-    case 5: return reinterpret_cast<const void *>(&vsample_kernel<1, 5>);
-    case 6: return reinterpret_cast<const void *>(&vsample_kernel<1, 6>);
-    case 7: return reinterpret_cast<const void *>(&vsample_kernel<1, 7>);
-    case 8: return reinterpret_cast<const void *>(&vsample_kernel<1, 8>);
-    case 9: return reinterpret_cast<const void *>(&vsample_kernel<1, 9>);
-    case 10: return reinterpret_cast<const void *>(&vsample_kernel<1, 10>);
-    case 11: return reinterpret_cast<const void *>(&vsample_kernel<1, 11>);
-    case 12: return reinterpret_cast<const void *>(&vsample_kernel<1, 12>);
-    case 13: return reinterpret_cast<const void *>(&vsample_kernel<1, 13>);
-    case 14: return reinterpret_cast<const void *>(&vsample_kernel<1, 14>);
-    case 15: return reinterpret_cast<const void *>(&vsample_kernel<1, 15>);
-    case 16: return reinterpret_cast<const void *>(&vsample_kernel<1, 16>);
+    case 1: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 1, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 1, false>);
+    case 2: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 2, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 2, false>);
+    case 3: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 3, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 3, false>);
+    case 4: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 4, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 4, false>);
+    case 5: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 5, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 5, false>);
+    case 6: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 6, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 6, false>);
+    case 7: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 7, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 7, false>);
+    case 8: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 8, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 8, false>);
+    case 9: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 9, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 9, false>);
+    case 10: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 10, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 10, false>);
+    case 11: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 11, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 11, false>);
+    case 12: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 12, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 12, false>);
+    case 13: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 13, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 13, false>);
+    case 14: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 14, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 14, false>);
+    case 15: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 15, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 15, false>);
+    case 16: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 16, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<1, 16, false>);
     default: return nullptr;
     }
 }

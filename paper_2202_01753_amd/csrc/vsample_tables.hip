@@ -23,21 +23,34 @@ hipError_t launch_sample_f3(int dim, int blocks, int threads, size_t lds_bytes,
     }
 }
 
-const void *sample_kernel_f3(int dim) {
+const void *sample_kernel_f3(int dim, bool trace) {
     switch (dim) {
-    case 4: return reinterpret_cast<const void *>(&vsample_kernel<3, 4>);
-    case 5: return reinterpret_cast<const void *>(&vsample_kernel<3, 5>);
-    case 6: return reinterpret_cast<const void *>(&vsample_kernel<3, 6>);
-    case 7: return reinterpret_cast<const void *>(&vsample_kernel<3, 7>);
-    case 8: return reinterpret_cast<const void *>(&vsample_kernel<3, 8>);
-    case 9: return reinterpret_cast<const void *>(&vsample_kernel<3, 9>);
-    case 10: return reinterpret_cast<const void *>(&vsample_kernel<3, 10>);
-    case 11: return reinterpret_cast<const void *>(&vsample_kernel<3, 11>);
-    case 12: return reinterpret_cast<const void *>(&vsample_kernel<3, 12>);
-    case 13: return reinterpret_cast<const void *>(&vsample_kernel<3, 13>);
-    case 14: return reinterpret_cast<const void *>(&vsample_kernel<3, 14>);
-    case 15: return reinterpret_cast<const void *>(&vsample_kernel<3, 15>);
-    case 16: return reinterpret_cast<const void *>(&vsample_kernel<3, 16>);
+    case 4: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 4, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 4, false>);
+    case 5: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 5, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 5, false>);
+    case 6: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 6, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 6, false>);
+    case 7: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 7, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 7, false>);
+    case 8: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 8, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 8, false>);
+    case 9: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 9, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 9, false>);
+    case 10: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 10, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 10, false>);
+    case 11: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 11, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 11, false>);
+    case 12: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 12, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 12, false>);
+    case 13: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 13, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 13, false>);
+    case 14: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 14, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 14, false>);
+    case 15: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 15, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 15, false>);
+    case 16: return trace ? reinterpret_cast<const void *>(&vsample_kernel<3, 16, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<3, 16, false>);
     default: return nullptr;
     }
 }
