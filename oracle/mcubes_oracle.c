@@ -39,6 +39,10 @@
  *   - Weighted estimate: inverse-variance weights over all iterations so far,
  *     chi^2 per degree of freedom about the weighted mean.
  *   - Convergence: at least two iterations and sigma <= tau_rel |I|.
+ *   - FP32-eval mode (precision 1): the uniform u = (2 (w[j] >> 9) + 1) 2^-24
+ *     from the same words, the map and the integrand in single precision
+ *     (constants, each bin's left boundary and width, and the tables rounded
+ *     to float from FP64), then I_k and everything after it in FP64 as above.
  *
  * Build with -ffp-contract=off: every rounding below is the one written.
  */
@@ -69,6 +73,7 @@ typedef struct {
     int32_t itmax, ita;
     double alpha, tau_rel;
     uint64_t seed;
+    int32_t precision;      /* 0: FP64, 1: FP32 evaluation with FP64 accumulation */
 } orc_problem;
 
 /* ------------------------------------------------------------------ */
@@ -104,6 +109,13 @@ double orc_uniform64(uint32_t whi, uint32_t wlo)
     uint64_t X = ((uint64_t)whi << 20) | (uint64_t)(wlo >> 12);
     uint64_t odd = 2u * X + 1u;            /* < 2^53: exact in a double */
     return (double)odd * 0x1p-53;
+}
+
+/* Single-precision uniform on (0,1) from the top 23 bits: (2 (w >> 9) + 1) 2^-24. */
+float orc_uniform24(uint32_t w)
+{
+    uint32_t odd = 2u * (w >> 9) + 1u;     /* < 2^24: exact in a float */
+    return (float)odd * 0x1p-24f;
 }
 
 /* ------------------------------------------------------------------ */
@@ -241,6 +253,63 @@ static double integrand_value(const orc_problem *P, const double *x)
     }
 }
 
+/* ---- single-precision evaluation (FP32-eval mode) ---- */
+
+typedef struct {
+    float lo[16], span[16], q[16], pa[16], pb[16];
+    float s, cval;
+    float *grid;     /* d*nb (left boundary, width) pairs rounded to float */
+    float *tables;   /* 2*256*256 rounded to float, or NULL */
+} f32_consts;
+
+static float lerpf_(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+static float table_bilinear_f(const float *T, float x, float y)
+{
+    float ux = x * 255.0f, uy = y * 255.0f;
+    float fa = floorf(ux), fb = floorf(uy);
+    if (fa < 0.0f) fa = 0.0f;
+    if (fa > 254.0f) fa = 254.0f;
+    if (fb < 0.0f) fb = 0.0f;
+    if (fb > 254.0f) fb = 254.0f;
+    float tx = ux - fa, ty = uy - fb;
+    int a = (int)fa, b = (int)fb;
+    float t00 = T[a * ORC_TABLE_N + b];
+    float t10 = T[(a + 1) * ORC_TABLE_N + b];
+    float t01 = T[a * ORC_TABLE_N + b + 1];
+    float t11 = T[(a + 1) * ORC_TABLE_N + b + 1];
+    return lerpf_(lerpf_(t00, t10, tx), lerpf_(t01, t11, tx), ty);
+}
+
+static float integrand_value_f(const orc_problem *P, const f32_consts *K, const float *x)
+{
+    int d = P->dim;
+    if (P->integrand == ORC_F_CONST) return K->cval;
+    if (P->integrand == ORC_F_CORNER_PEAK) {
+        float S = 1.0f;
+        for (int j = 0; j < d; ++j) S = fmaf(K->pa[j], x[j], S);
+        unsigned e = (unsigned)(d + 1);
+        int top = 31;
+        while (!((e >> top) & 1u)) --top;
+        float pw = S;
+        for (int bit = top - 1; bit >= 0; --bit) {
+            pw = pw * pw;
+            if ((e >> bit) & 1u) pw = pw * S;
+        }
+        return 1.0f / pw;
+    }
+    float acc = 0.0f;
+    for (int j = 0; j < d; ++j) {
+        float t = (x[j] - K->pa[j]) * K->pb[j];
+        acc = fmaf(t, t, acc);
+    }
+    float G = expf(-acc);
+    if (P->integrand == ORC_F_GAUSS_PRODUCT) return G;
+    float T1 = table_bilinear_f(K->tables, x[0], x[1]);
+    float T2 = table_bilinear_f(K->tables + ORC_TABLE_N * ORC_TABLE_N, x[2], x[3]);
+    return (G * T1) * T2;
+}
+
 static int validate(const orc_problem *P)
 {
     int d = P->dim;
@@ -249,6 +318,7 @@ static int validate(const orc_problem *P)
     if (P->maxcalls < 4) return ORC_EINVAL;
     if (P->itmax < 1 || P->ita < 0 || P->ita > P->itmax) return ORC_EINVAL;
     if (!(P->alpha > 0.0) || !(P->tau_rel >= 0.0)) return ORC_EINVAL;
+    if (P->precision != 0 && P->precision != 1) return ORC_EINVAL;
     if (params_expected(P->integrand, d) < 0) return ORC_EINVAL;
     if (P->integrand == ORC_F_GAUSS_TABLES && (d < 4 || P->tables == NULL)) return ORC_EINVAL;
     for (int j = 0; j < d; ++j)
@@ -346,6 +416,41 @@ int orc_vsample(const orc_problem *P, uint32_t iter, const double *grid, int64_t
         q[j] = (double)nb * span[j];
     }
 
+    const int fp32 = P->precision == 1;
+    if (fp32 && g > (1 << 24)) return ORC_EINVAL; /* cube digits must be exact floats */
+    f32_consts K;
+    memset(&K, 0, sizeof(K));
+    if (fp32) {
+        K.s = (float)s;
+        for (int j = 0; j < d; ++j) {
+            K.lo[j] = (float)P->lo[j];
+            K.span[j] = (float)span[j];
+            K.q[j] = (float)q[j];
+        }
+        if (P->integrand == ORC_F_CONST) K.cval = (float)P->params[0];
+        if (P->integrand == ORC_F_CORNER_PEAK)
+            for (int j = 0; j < d; ++j) K.pa[j] = (float)P->params[j];
+        if (P->integrand == ORC_F_GAUSS_PRODUCT || P->integrand == ORC_F_GAUSS_TABLES)
+            for (int j = 0; j < d; ++j) {
+                K.pa[j] = (float)P->params[j];
+                K.pb[j] = (float)(1.0 / P->params[d + j]);
+            }
+        /* per bin: left boundary and width, each rounded once from FP64 */
+        K.grid = (float *)malloc(sizeof(float) * 2 * d * nb);
+        for (int j = 0; j < d; ++j)
+            for (int i = 0; i < nb; ++i) {
+                const double *B = grid + (size_t)j * (nb + 1);
+                K.grid[2 * ((size_t)j * nb + i)] = (float)B[i];
+                K.grid[2 * ((size_t)j * nb + i) + 1] = (float)(B[i + 1] - B[i]);
+            }
+        if (P->integrand == ORC_F_GAUSS_TABLES) {
+            K.tables = (float *)malloc(sizeof(float) * 2 * ORC_TABLE_N * ORC_TABLE_N);
+            for (int i = 0; i < 2 * ORC_TABLE_N * ORC_TABLE_N; ++i) K.tables[i] = (float)P->tables[i];
+        }
+    }
+    /* FP32 needs one word per axis, FP64 two; the counter layout is the same */
+    const int blocks_used = fp32 ? (d + 3) / 4 : nblk;
+
     nsum *bins = NULL;
     if (hist) {
         bins = (nsum *)calloc((size_t)d * nb, sizeof(nsum));
@@ -365,19 +470,48 @@ int orc_vsample(const orc_problem *P, uint32_t iter, const double *grid, int64_t
         double I0 = 0.0, S1 = 0.0, S2 = 0.0;
         for (int64_t k = 0; k < p; ++k) {
             uint32_t w[32];
-            for (int blk = 0; blk < nblk; ++blk) {
+            for (int blk = 0; blk < blocks_used; ++blk) {
                 uint32_t ctr[4] = {(uint32_t)(k * nblk + blk), iter, (uint32_t)t, (uint32_t)((uint64_t)t >> 32)};
                 orc_philox4x32_10(ctr, key, w + 4 * blk);
             }
             double u[16], z[16], x[16];
             int64_t bin[16];
-            for (int j = 0; j < d; ++j) {
-                u[j] = orc_uniform64(w[j], w[d + j]);
-                double v = (double)digit[j] + u[j];
-                z[j] = v * s;
+            double J, f;
+            if (!fp32) {
+                for (int j = 0; j < d; ++j) {
+                    u[j] = orc_uniform64(w[j], w[d + j]);
+                    double v = (double)digit[j] + u[j];
+                    z[j] = v * s;
+                }
+                J = map_point(d, nb, grid, P->lo, span, q, z, x, bin);
+                f = integrand_value(P, x);
+            } else {
+                float xf[16], Jf = 1.0f;
+                for (int j = 0; j < d; ++j) {
+                    float uf = orc_uniform24(w[j]);
+                    float zf = ((float)digit[j] + uf) * K.s;
+                    float fz = floorf(zf);
+                    int64_t i = (int64_t)fz;
+                    float frac;
+                    if (i > nb - 1) {
+                        i = nb - 1;
+                        frac = 1.0f;
+                    } else {
+                        frac = zf - fz;
+                    }
+                    const float *cell = K.grid + 2 * ((size_t)j * nb + i);
+                    float left = cell[0];
+                    float width = cell[1];
+                    float xu = fmaf(frac, width, left);
+                    xf[j] = fmaf(K.span[j], xu, K.lo[j]);
+                    Jf = Jf * (width * K.q[j]);
+                    bin[j] = i;
+                    u[j] = (double)uf;
+                    x[j] = (double)xf[j];
+                }
+                J = (double)Jf;
+                f = (double)integrand_value_f(P, &K, xf);
             }
-            double J = map_point(d, nb, grid, P->lo, span, q, z, x, bin);
-            double f = integrand_value(P, x);
             if (!isfinite(f)) nonfinite = 1;
             double F = f * J;
             double Ik = F * inv;
@@ -414,6 +548,8 @@ int orc_vsample(const orc_problem *P, uint32_t iter, const double *grid, int64_t
             ctrace[2 * (t - t0) + 1] = vt;
         }
     }
+    free(K.grid);
+    free(K.tables);
     *out_I = nsum_value(&total_I);
     *out_var = nsum_value(&total_V);
     if (bins) {

@@ -7,7 +7,8 @@ imports it.  It imports nothing from the GPU package.
 A problem is a plain dict with the keys ``integrand`` (one of "const",
 "gauss_product", "corner_peak", "gauss_tables"), ``params``, ``tables``
 (or None), ``dim``, ``lo``, ``hi``, ``maxcalls``, ``nbins``, ``itmax``,
-``ita``, ``alpha``, ``tau_rel`` and ``seed``.
+``ita``, ``alpha``, ``tau_rel``, ``seed`` and optionally ``precision``
+("fp64", the default, or "fp32" for FP32 evaluation with FP64 accumulation).
 """
 from __future__ import annotations
 
@@ -46,6 +47,7 @@ class _Problem(C.Structure):
         ("alpha", C.c_double),
         ("tau_rel", C.c_double),
         ("seed", C.c_uint64),
+        ("precision", C.c_int32),
     ]
 
 
@@ -76,6 +78,8 @@ def lib():
         L.orc_philox4x32_10.restype = None
         L.orc_uniform64.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_uniform64.restype = C.c_double
+        L.orc_uniform24.argtypes = [C.c_uint32]
+        L.orc_uniform24.restype = C.c_float
         L.orc_shape.argtypes = [C.c_int32, C.c_int64] + [C.POINTER(C.c_int64)] * 3
         L.orc_shape.restype = C.c_int
         L.orc_integrand.argtypes = [C.POINTER(_Problem), dp]
@@ -119,7 +123,8 @@ class _Bound:
             INTEGRANDS[prob["integrand"]], _dp(self.params), _dp(self.tables), int(prob["dim"]),
             _dp(self.lo), _dp(self.hi), int(prob["maxcalls"]), int(prob["nbins"]),
             int(prob["itmax"]), int(prob.get("ita", prob["itmax"])), float(prob["alpha"]),
-            float(prob.get("tau_rel", 0.0)), int(prob["seed"]) & (2**64 - 1))
+            float(prob.get("tau_rel", 0.0)), int(prob["seed"]) & (2**64 - 1),
+            1 if prob.get("precision", "fp64") == "fp32" else 0)
 
 
 def philox4x32_10(ctr, key):
@@ -132,6 +137,10 @@ def philox4x32_10(ctr, key):
 
 def uniform64(whi: int, wlo: int) -> float:
     return lib().orc_uniform64(whi & 0xFFFFFFFF, wlo & 0xFFFFFFFF)
+
+
+def uniform24(w: int) -> float:
+    return lib().orc_uniform24(w & 0xFFFFFFFF)
 
 
 def shape(d: int, maxcalls: int):

@@ -46,21 +46,36 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
     c = (c + c2) + e;
 }
 
-// Blocks [0, nhb): one bin per thread, the workgroup partials summed in
-// workgroup order.  Block nhb: the totals, each thread summing a strided
-// subset of workgroups in order, then a fixed pairwise tree.
+constexpr int kFinBins = 32;                  // bins per histogram block
+constexpr int kFinGroups = kFinThreads / kFinBins;  // workgroup-row groups per bin
+
+// Blocks [0, nhb): kFinBins bins per block; for each bin, group q sums the
+// workgroup rows q, q + kFinGroups, ... in order and the groups are merged in
+// order, so the result depends only on the number of workgroups.  Block nhb:
+// the totals, each thread summing a strided subset of workgroups in order,
+// then a fixed pairwise tree.  All merges are TwoSum-compensated.
 __global__ void __launch_bounds__(kFinThreads)
 finalize_kernel(const double *__restrict__ part, int blocks, int nhist, int hist_stride, int nhb,
                 uint32_t *flag, double *out) {
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < nhb) {
-        const int b = blockIdx.x * kFinThreads + tid;
-        if (b >= nhist) return;
-        const double *col = part + 4 * (size_t)blocks + b;
+        __shared__ double gs[kFinGroups][kFinBins], gc[kFinGroups][kFinBins];
+        const int lane = tid % kFinBins, grp = tid / kFinBins;
+        const int b = blockIdx.x * kFinBins + lane;
         double s = 0.0, c = 0.0;
-#pragma unroll 8
-        for (int w = 0; w < blocks; ++w) two_sum_merge(s, c, col[(size_t)w * hist_stride], 0.0);
-        out[4 + b] = s + c;
+        if (b < nhist) {
+            const double *col = part + 4 * (size_t)blocks + b;
+#pragma unroll 4
+            for (int w = grp; w < blocks; w += kFinGroups)
+                two_sum_merge(s, c, col[(size_t)w * hist_stride], 0.0);
+        }
+        gs[grp][lane] = s;
+        gc[grp][lane] = c;
+        __syncthreads();
+        if (grp == 0 && b < nhist) {
+            for (int q = 1; q < kFinGroups; ++q) two_sum_merge(s, c, gs[q][lane], gc[q][lane]);
+            out[4 + b] = s + c;
+        }
         return;
     }
     __shared__ double red[kFinThreads][4];
@@ -97,7 +112,7 @@ __global__ void clear_flag_kernel(uint32_t *flag) { *flag = 0u; }
 
 hipError_t launch_finalize(const double *partials, int blocks, int nhist, int hist_stride,
                            int with_hist, uint32_t *flag, double *out, hipStream_t stream) {
-    const int nhb = with_hist ? (nhist + kFinThreads - 1) / kFinThreads : 0;
+    const int nhb = with_hist ? (nhist + kFinBins - 1) / kFinBins : 0;
     hipLaunchKernelGGL(finalize_kernel, dim3(nhb + 1), dim3(kFinThreads), 0, stream, partials,
                        blocks, nhist, hist_stride, nhb, flag, out);
     return hipGetLastError();

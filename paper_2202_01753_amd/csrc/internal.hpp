@@ -30,6 +30,7 @@ struct SampleArgs {
     int32_t hist;           // nonzero: collect bin contributions (V-Sample)
     int32_t hist_stride;    // doubles between two workgroups' histograms in partials
     double s;               // nb / g
+    double nb_minus1;       // nb - 1
     double inv;             // 1 / (m p)
     double pd;              // p
     double inv_pm1;         // 1 / (p - 1)

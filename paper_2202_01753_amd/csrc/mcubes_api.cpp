@@ -9,9 +9,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -183,6 +188,127 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     return MC_OK;
 }
 
+// ------------------------------------------------------------------ host worker threads
+
+// A few host threads that take the axes of one bin adjustment in parallel
+// (axes are independent, so the result does not depend on the split).  The
+// jobs are short (tens of microseconds), so the driver primes the pool while
+// it waits for the GPU: primed workers spin for a bounded time instead of
+// sleeping, and a job is picked up within microseconds.  Tasks are tickets
+// (generation << 32 | index), so a worker that wakes late for an old job can
+// never take a task of a newer one.  One job at a time; a caller that finds
+// the pool busy runs its job alone.
+class AxisPool {
+  public:
+    static AxisPool &get() {
+        static AxisPool pool;
+        return pool;
+    }
+
+    // Workers spin (rather than sleep) for the next `us` microseconds.
+    void prime(int us) {
+        if (!start_workers()) return;
+        spin_until_.store(now_ns() + (int64_t)us * 1000, std::memory_order_release);
+        std::lock_guard<std::mutex> lk(mu_);
+        cv_.notify_all();
+    }
+
+    void run(int n, const std::function<void(int)> &fn) {
+        std::unique_lock<std::mutex> job_lock(job_mu_, std::try_to_lock);
+        if (n < 2 || !job_lock.owns_lock() || !start_workers()) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        const uint64_t gen = gen_.load(std::memory_order_relaxed) + 1;
+        job_.store(&fn, std::memory_order_relaxed);
+        n_.store(n, std::memory_order_relaxed);
+        remaining_.store(n, std::memory_order_relaxed);
+        ticket_.store(gen << 32, std::memory_order_relaxed);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            gen_.store(gen, std::memory_order_release);
+        }
+        cv_.notify_all();
+        drain(gen);
+        while (remaining_.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    }
+
+    ~AxisPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_.store(true);
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+
+  private:
+    static int64_t now_ns() {
+        return std::chrono::duration_cast<std::chrono::nanoseconds>(
+                   std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+
+    bool start_workers() {
+        std::lock_guard<std::mutex> lk(start_mu_);
+        if (!workers_.empty()) return true;
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int count = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 7);
+        try {
+            for (int i = 0; i < count; ++i) workers_.emplace_back([this] { loop(); });
+        } catch (...) {
+        }
+        return !workers_.empty();
+    }
+
+    void drain(uint64_t gen) {
+        for (;;) {
+            uint64_t t = ticket_.load(std::memory_order_acquire);
+            if ((t >> 32) != gen) return;
+            const uint32_t i = (uint32_t)t;
+            if ((int)i >= n_.load(std::memory_order_relaxed)) return;
+            if (!ticket_.compare_exchange_weak(t, t + 1, std::memory_order_acq_rel)) continue;
+            (*job_.load(std::memory_order_relaxed))((int)i);
+            remaining_.fetch_sub(1, std::memory_order_release);
+        }
+    }
+
+    void loop() {
+        uint64_t seen = gen_.load(std::memory_order_acquire);
+        for (;;) {
+            uint64_t g = gen_.load(std::memory_order_acquire);
+            while (g == seen && !stop_.load() && now_ns() < spin_until_.load(std::memory_order_acquire)) {
+                std::this_thread::yield();
+                g = gen_.load(std::memory_order_acquire);
+            }
+            if (g == seen) {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] {
+                    return stop_.load() || gen_.load(std::memory_order_acquire) != seen ||
+                           now_ns() < spin_until_.load(std::memory_order_acquire);
+                });
+                if (stop_.load()) return;
+                continue;
+            }
+            if (stop_.load()) return;
+            seen = g;
+            drain(g);
+        }
+    }
+
+    std::mutex job_mu_, mu_, start_mu_;
+    std::condition_variable cv_;
+    std::vector<std::thread> workers_;
+    // job_ and n_ are read by workers only after they acquire the generation that
+    // published them; a worker still holding an older generation may read them
+    // too, but its ticket compare-exchange then fails.
+    std::atomic<const std::function<void(int)> *> job_{nullptr};
+    std::atomic<int> n_{0};
+    std::atomic<int> remaining_{0};
+    std::atomic<uint64_t> gen_{0}, ticket_{0};
+    std::atomic<int64_t> spin_until_{0};
+    std::atomic<bool> stop_{false};
+};
+
 // ------------------------------------------------------------------ one sampling pass
 
 void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter, bool adjust,
@@ -206,6 +332,7 @@ void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter,
     a->hist = adjust ? 1 : 0;
     a->hist_stride = G.hist_stride;
     a->s = (double)nb / (double)G.g;
+    a->nb_minus1 = (double)(nb - 1);
     a->inv = 1.0 / (double)(G.m * G.p);
     a->pd = (double)G.p;
     a->inv_pm1 = 1.0 / (a->pd - 1.0);
@@ -241,7 +368,7 @@ struct Events {
 mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t stream,
                    uint32_t iter, bool adjust, const double *h_grid, double *out_host,
                    double *trace, int64_t t0, int64_t t1, Events *ev, double *ms_sample,
-                   double *ms_fin) {
+                   double *ms_fin, int spin_us = 0) {
     const int d = pr->dim, nb = pr->nbins;
     const int blocks = adjust ? G.blocks_adj : G.blocks_noadj;
     const size_t lds = adjust ? G.lds_adj : G.lds_noadj;
@@ -260,6 +387,7 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     HIP_TRY(launch_finalize(a.partials, blocks, d * nb, G.hist_stride, adjust ? 1 : 0, a.flag,
                             out_dev, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[2], stream));
+    if (adjust && d > 1) AxisPool::get().prime(spin_us);
     const size_t nout = 4 + (adjust ? (size_t)d * nb : 0);
     HIP_TRY(hipMemcpyAsync(out_host, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -357,9 +485,10 @@ void refine_axis(int nb, double alpha, const double *C, double *B, std::vector<d
 }
 
 void refine(int d, int nb, double alpha, const double *hist, double *grid) {
-    std::vector<double> sm(nb), r(nb), prev(nb + 1);
-    for (int j = 0; j < d; ++j)
+    AxisPool::get().run(d, [&](int j) {
+        std::vector<double> sm(nb), r(nb), prev(nb + 1);
         refine_axis(nb, alpha, hist + (size_t)j * nb, grid + (size_t)j * (nb + 1), sm, r, prev);
+    });
 }
 
 void weighted(int k, const double *I, const double *var, double *out) {
@@ -504,11 +633,16 @@ mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void
     if (timing) HIP_TRY(ev.create());
     double ms_s = 0.0, ms_f = 0.0, est[3] = {0.0, 0.0, NAN};
     int k = 0, converged = 0;
+    int spin_us = 0;  // how long primed refinement threads spin: about one pass
     for (int it = 0; it < prob->itmax; ++it) {
         const bool adjust = it < prob->ita;
+        const auto pass_start = std::chrono::steady_clock::now();
         st = run_pass(prob, G, ws, s, (uint32_t)it, adjust, grid.data(), buf.data(), nullptr, 0, 0,
-                      timing ? &ev : nullptr, &ms_s, &ms_f);
+                      timing ? &ev : nullptr, &ms_s, &ms_f, spin_us);
         if (st != MC_OK) return st;
+        const double pass_us = std::chrono::duration<double, std::micro>(
+                                   std::chrono::steady_clock::now() - pass_start).count();
+        spin_us = (int)std::min(2.0 * pass_us + 200.0, 20000.0);
         Is[it] = buf[0];
         Vs[it] = buf[1];
         k = it + 1;

@@ -207,13 +207,12 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
             for (int j = 0; j < D; ++j) {
                 const double u = uniform53(w[j], w[D + j]);
                 const double z = (cd[j] + u) * a.s;
-                const double fz = floor(z);
-                int i = (int)fz;
-                double frac = z - fz;
-                if (i > nb - 1) {
-                    i = nb - 1;
-                    frac = 1.0;
-                }
+                // bin index, clamped to the last bin with fraction 1 there: once
+                // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
+                // gives exactly 1; otherwise z - floor(z) < 1 is exact.
+                const double fz = fmin(floor(z), a.nb_minus1);
+                const int i = (int)fz;
+                const double frac = fmin(z - fz, 1.0);
                 const double *B = sB + j * row + i;
                 const double left = B[0];
                 const double width = B[1] - left;

@@ -436,3 +436,76 @@ def test_invalid_problems_rejected():
     inf = W.const(2, np.inf, maxcalls=100, nbins=10, itmax=1)
     r = O.integrate(inf, check=False)
     assert r["status"] == O.ENONFINITE
+
+
+# ---------------------------------------------------------------- FP32-eval mode
+
+def test_uniform24_endpoints_and_agreement_with_uniform53():
+    assert O.uniform24(0) == 2.0**-24
+    assert O.uniform24(0xFFFFFFFF) == 1.0 - 2.0**-24
+    assert O.uniform24(0x80000000) == 0.5 + 2.0**-24
+    assert O.uniform24(0x1FF) == O.uniform24(0)  # only the top 23 bits enter
+    rng = np.random.default_rng(9)
+    for a, b in rng.integers(0, 2**32, size=(500, 2)):
+        u32, u64 = O.uniform24(int(a)), O.uniform64(int(a), int(b))
+        assert 0.0 < u32 < 1.0 and abs(u32 - u64) <= 2.0**-24
+
+
+def _fp32(prob):
+    q = dict(prob)
+    q["precision"] = "fp32"
+    return q
+
+
+def test_fp32_constant_dyadic_exact():
+    prob = _fp32(_dyadic_const(lo=(0.0, 0.0), hi=(1.0, 1.0)))
+    nb = prob["nbins"]
+    r = O.vsample(prob, 0, O.init_grid(2, nb), trace=True)
+    assert r["I"] == 2.5 and r["var"] == 0.0
+    # on the uniform dyadic grid the point is the stratified coordinate itself
+    st = r["strace"]
+    g, m, p = O.shape(2, prob["maxcalls"])
+    t = np.repeat(np.arange(m), p)
+    for j in range(2):
+        c = ((t // g**j) % g).astype(np.float32)
+        z = (c + st[:, j].astype(np.float32)) * np.float32(nb / g)
+        assert np.array_equal(st[:, 4 + j], (z / np.float32(nb)).astype(np.float64))
+        assert np.array_equal(st[:, 2 + j], np.floor(z).astype(np.float64))
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.config_small(seed=3),
+    lambda: W.corner_peak(3, 5, maxcalls=20_000, nbins=50, itmax=6, seed=4),
+    lambda: W.config_tables(seed=5, maxcalls=200_000, itmax=4),
+])
+def test_fp32_eval_tracks_fp64_on_the_same_samples(make):
+    prob = make()
+    d, nb = prob["dim"], prob["nbins"]
+    rng = np.random.default_rng(2)
+    grid = np.concatenate([_random_grid(rng, nb) for _ in range(d)])
+    # one pass on a fixed grid: the two precisions sample points 2^-24 apart
+    a = O.vsample(prob, 0, grid, hist=False)
+    b = O.vsample(_fp32(prob), 0, grid, hist=False)
+    assert abs(b["I"] - a["I"]) <= 1e-5 * abs(a["I"])
+    assert abs(b["var"] - a["var"]) <= 1e-4 * a["var"]
+    # whole adaptive runs diverge after the first refinement (a sample that
+    # lands on the other side of a bin edge changes the histogram), so they
+    # agree statistically and each is an accurate estimate
+    a, b = O.integrate(prob), O.integrate(_fp32(prob))
+    assert abs(b["estimate"] - a["estimate"]) < 5 * math.hypot(a["error"], b["error"])
+    assert abs(b["estimate"] - CF.exact(prob)) < 4.5 * b["error"]
+
+
+def test_fp32_estimator_unbiased():
+    prob = _fp32(W.corner_peak(2, 8, maxcalls=2000, nbins=20))
+    exact = CF.exact(prob)
+    rng = np.random.default_rng(4)
+    grid = np.concatenate([_random_grid(rng, 20), _random_grid(rng, 20)])
+    n = 400
+    Is, Vs = np.zeros(n), np.zeros(n)
+    for s in range(n):
+        prob["seed"] = 7000 + s
+        r = O.vsample(prob, 0, grid, hist=False)
+        Is[s], Vs[s] = r["I"], r["var"]
+    assert abs(Is.mean() - exact) < 4 * Is.std(ddof=1) / math.sqrt(n)
+    assert abs(Vs.mean() / Is.var(ddof=1) - 1.0) < 0.25
