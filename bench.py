@@ -166,15 +166,50 @@ def main():
     achieved = ops / avg_launch_s
     r0 = results[0]
 
-    # time to a 1e-3 relative error on the same workload (FP64 path)
-    prob_t = dict(prob)
-    prob_t["tau_rel"] = 1e-3
-    bpt = M.BoundProblem(prob_t, args.blocks, args.threads)
+    def time_to_target(precision):
+        """Wall time of one run to a 1e-3 relative error, after one untimed run."""
+        pt = dict(prob, tau_rel=1e-3, precision=precision, seed=77)
+        bpt = M.BoundProblem(pt, args.blocks, args.threads)
+        wst = M.Workspace(bpt)
+        M.integrate(pt, ws=wst, bp=bpt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = M.integrate(pt, ws=wst, bp=bpt)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    rt, tt = time_to_target("fp64")
+
+    # the FP32-evaluation path on the same workload: throughput, time to 1e-3,
+    # and its distance from the FP64 run with the same seed
+    p32 = dict(prob, precision="fp32")
+    bp32 = M.BoundProblem(p32, args.blocks, args.threads)
+    ws32 = M.Workspace(bp32)
+    for w in range(args.warmup):
+        p32["seed"] = bp32.s.seed = 1000 + w
+        M.integrate(p32, ws=ws32, bp=bp32)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rt = M.integrate(prob_t, ws=ws, bp=bpt)
+    res32 = []
+    t2 = time.perf_counter()
+    for k in range(args.steps):
+        p32["seed"] = bp32.s.seed = 1 + k
+        res32.append(M.integrate(p32, ws=ws32, bp=bp32, timing=True))
     torch.cuda.synchronize()
-    tt = time.perf_counter() - t1
+    el32 = time.perf_counter() - t2
+    rt32, tt32 = time_to_target("fp32")
+    k32 = sum(r.sample_ms for r in res32) / sum(r.iterations for r in res32) / 1e3
+    fp32_eval = {
+        "value": sum(r.calls for r in res32) / el32, "unit": "samples/s",
+        "ms_per_step": el32 / args.steps * 1e3, "kernel_samples_per_s": calls_per_iter / k32,
+        "avg_launch_ms": k32 * 1e3,
+        "time_to_1e-3": {"ms": tt32 * 1e3, "iterations": rt32.iterations,
+                         "converged": rt32.converged, "estimate": rt32.estimate,
+                         "rel_error": rt32.error / abs(rt32.estimate)},
+        "vs_fp64_same_seed": {
+            "rel_diff": (res32[0].estimate - results[0].estimate) / abs(results[0].estimate),
+            "in_sigma": (res32[0].estimate - results[0].estimate)
+                        / math.hypot(res32[0].error, results[0].error)},
+    }
 
     line = {
         "metric": "integrand samples/sec/GPU",
@@ -204,6 +239,7 @@ def main():
         "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
                          "estimate": rt.estimate, "rel_error": rt.error / abs(rt.estimate)},
         "estimate": {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof},
+        "fp32_eval": fp32_eval,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob)

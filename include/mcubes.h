@@ -54,7 +54,11 @@ typedef int32_t mc_status;
 #define MC_F_CORNER_PEAK 2
 #define MC_F_GAUSS_TABLES 3
 
-#define MC_FP64 0 /* all arithmetic in FP64 */
+#define MC_FP64 0      /* all arithmetic in FP64 */
+#define MC_FP32_EVAL 1 /* the map and the integrand in FP32 (uniforms from the top 23 bits of
+                          the same random words; constants, bin edges and widths, and tables
+                          rounded to float); I_k, per-cube and per-bin sums, the weighted
+                          estimate and the bin adjustment in FP64.  Needs g <= 2^24. */
 
 #define MC_MAX_DIM 16
 
@@ -75,7 +79,7 @@ typedef struct mc_problem {
     int32_t nbins;           /* nb, bins per axis, >= 2 */
     int32_t itmax;           /* iterations, >= 1 */
     int32_t ita;             /* adjusting iterations, 0..itmax */
-    int32_t precision;       /* MC_FP64 */
+    int32_t precision;       /* MC_FP64 or MC_FP32_EVAL */
     double alpha;            /* damping exponent of the bin adjustment, > 0 */
     double tau_rel;          /* target relative error; 0 runs all itmax iterations */
     uint64_t seed;           /* random-number key */
@@ -164,6 +168,76 @@ mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var
  *   timing   host or NULL */
 mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
                        mc_result *out, double *h_iters, double *h_grid, mc_timing *timing);
+
+/* ---------------------------------------------------------------- batches and serving
+ *
+ * Many independent integrals advanced together.  Every step runs one sampling
+ * pass (V-Sample or V-Sample-No-Adjust, per integral) of every active
+ * integral in one persistent launch per precision present, merges each
+ * integral's pieces in a fixed order, adjusts the grids of the integrals
+ * still in their adjusting iterations on the device (the same steps as
+ * mc_refine_grid, with the device library's pow and log), and then runs
+ * Weighted-Estimates and Check-Convergence per integral on the host.  Grids,
+ * histograms and tables stay in device memory.  Each integral's random
+ * numbers depend only on its own seed, iteration, cube and sample, so an
+ * integral gets the same samples alone and in any mix.
+ *
+ * Integrals in a batch or a server have dim <= MC_BATCH_MAX_DIM; everything
+ * else is as for mc_integrate. */
+#define MC_BATCH_MAX_DIM 10
+
+#define MC_REQ_QUEUED 0   /* submitted, waiting for device memory */
+#define MC_REQ_RUNNING 1  /* admitted: iterating */
+#define MC_REQ_DONE 2     /* converged or ran itmax iterations; result available */
+#define MC_REQ_FAILED 3   /* stopped with an error status (e.g. MC_ENONFINITE) */
+
+typedef struct mc_batch_stats {
+    int32_t steps;       /* persistent sampling steps */
+    int32_t max_active;  /* most integrals in one step */
+    double sample_ms;    /* sampling-launch time summed over steps (HIP events) */
+    double step_ms;      /* host wall time of the steps */
+    int64_t calls;       /* integrand evaluations over all integrals */
+} mc_batch_stats;
+
+/* Device workspace for running the n problems together with
+ * mc_batch_integrate.  MC_EINVAL for an invalid problem or dim above
+ * MC_BATCH_MAX_DIM; MC_EDEVICE without a usable device. */
+mc_status mc_batch_workspace_bytes(const mc_problem *probs, int32_t n, size_t *bytes);
+
+/* Runs the n problems to completion together (one persistent sampling launch
+ * per step).  Synchronous.  results[i] is written when statuses[i] is MC_OK;
+ * statuses[i] is MC_ENONFINITE for an integral whose integrand produced a
+ * non-finite value (the others are unaffected).  The return value is MC_OK
+ * unless the whole batch failed (invalid input, workspace, device). */
+mc_status mc_batch_integrate(const mc_problem *probs, int32_t n, void *d_ws, size_t ws_bytes,
+                             void *stream, mc_result *results, mc_status *statuses,
+                             mc_batch_stats *stats);
+
+/* A serving loop with continuous batching over a caller-owned workspace.
+ * The first arena_bytes of the workspace hold admitted integrals' persistent
+ * state (constants, tables, two grids and the latest histogram per
+ * integral); the rest holds one step's work tables.  Requests are admitted
+ * in arrival order when both fit, at most max_active at a time.  One server
+ * must not be used from two threads at once. */
+typedef struct mc_server mc_server;
+
+mc_status mc_server_create(void *d_ws, size_t ws_bytes, size_t arena_bytes, int32_t max_active,
+                           void *stream, mc_server **out);
+/* Copies the problem (host arrays included) and queues it.  MC_EWORKSPACE if
+ * it could never fit, even alone. */
+mc_status mc_server_submit(mc_server *srv, const mc_problem *prob, int64_t *id);
+/* Admits what fits, runs one step over the active requests, retires the
+ * finished ones.  active/queued/finished (each may be NULL) report the counts
+ * after the step. */
+mc_status mc_server_step(mc_server *srv, int32_t *active, int32_t *queued, int32_t *finished);
+/* State (MC_REQ_*) of a request; out is written when it is MC_REQ_DONE and
+ * status (may be NULL) holds its final status. */
+mc_status mc_server_poll(mc_server *srv, int64_t id, int32_t *state, mc_result *out,
+                         mc_status *status);
+/* Forgets a finished request. */
+mc_status mc_server_release(mc_server *srv, int64_t id);
+mc_status mc_server_stats(mc_server *srv, mc_batch_stats *stats);
+mc_status mc_server_destroy(mc_server *srv);
 
 #ifdef __cplusplus
 }

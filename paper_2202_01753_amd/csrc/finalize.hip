@@ -8,17 +8,17 @@ hipError_t launch_sample_f0(int, int, int, size_t, hipStream_t, const SampleArgs
 hipError_t launch_sample_f1(int, int, int, size_t, hipStream_t, const SampleArgs &);
 hipError_t launch_sample_f2(int, int, int, size_t, hipStream_t, const SampleArgs &);
 hipError_t launch_sample_f3(int, int, int, size_t, hipStream_t, const SampleArgs &);
-const void *sample_kernel_f0(int, bool);
-const void *sample_kernel_f1(int, bool);
-const void *sample_kernel_f2(int, bool);
-const void *sample_kernel_f3(int, bool);
+const void *sample_kernel_f0(int, bool, bool);
+const void *sample_kernel_f1(int, bool, bool);
+const void *sample_kernel_f2(int, bool, bool);
+const void *sample_kernel_f3(int, bool, bool);
 
-const void *sample_kernel(int integrand, int dim, bool trace) {
+const void *sample_kernel(int integrand, int dim, bool trace, bool fp32) {
     switch (integrand) {
-    case 0: return sample_kernel_f0(dim, trace);
-    case 1: return sample_kernel_f1(dim, trace);
-    case 2: return sample_kernel_f2(dim, trace);
-    case 3: return sample_kernel_f3(dim, trace);
+    case 0: return sample_kernel_f0(dim, trace, fp32);
+    case 1: return sample_kernel_f1(dim, trace, fp32);
+    case 2: return sample_kernel_f2(dim, trace, fp32);
+    case 3: return sample_kernel_f3(dim, trace, fp32);
     default: return nullptr;
     }
 }

@@ -10,12 +10,14 @@ namespace mcubes {
 constexpr int kMaxDim = 16;
 constexpr int kTableN = 256;
 constexpr int kMaxBlock = 1024;
+constexpr int kBatchBlock = 256;     // threads per workgroup of the batched kernel
+constexpr int kBatchMaxDim = 10;     // dimensions the batched kernel supports
 
 // Everything the sampling kernel needs, passed by value so that the per-axis
 // constants arrive in scalar registers.
 struct SampleArgs {
     const double *grid;     // dim*(nb+1) boundaries, unit coordinates
-    const double *tables;   // 2*256*256 (gauss-tables integrand) or nullptr
+    const void *tables;     // 2*256*256 of the evaluation precision, or nullptr
     double *partials;       // per workgroup: 4 totals, then (optional) dim*nb bins
     uint32_t *flag;         // set to nonzero when the integrand is not finite
     double *trace;          // optional per-sample / per-cube records
@@ -29,13 +31,15 @@ struct SampleArgs {
     int32_t g;              // intervals per axis
     int32_t hist;           // nonzero: collect bin contributions (V-Sample)
     int32_t hist_stride;    // doubles between two workgroups' histograms in partials
+    int32_t kind;           // integrand id * 32 + dim (dispatch in the batched kernel)
     double s;               // nb / g
-    double nb_minus1;       // nb - 1
+    float s32;              // nb / g rounded to float (FP32 evaluation)
+    int32_t fp32;           // nonzero: FP32 evaluation
     double inv;             // 1 / (m p)
     double pd;              // p
     double inv_pm1;         // 1 / (p - 1)
     double cval;            // constant integrand value
-    const double *consts;   // kConstStride doubles per axis, see below
+    const void *consts;     // kConstStride values of the evaluation precision per axis
     int32_t sdig[kMaxDim];  // stride in base g, least significant digit first
 };
 
@@ -44,8 +48,8 @@ struct SampleArgs {
 //   [3] Gaussian centre or corner-peak coefficient   [4] Gaussian 1/width   [5] 0
 constexpr int kConstStride = 6;
 
-// Returns the sampling kernel for (integrand, dim) and its tracing variant, or nullptr.
-const void *sample_kernel(int integrand, int dim, bool trace);
+// Returns the sampling kernel for (integrand, dim, trace, FP32 evaluation), or nullptr.
+const void *sample_kernel(int integrand, int dim, bool trace, bool fp32);
 
 // Launches the sampling kernel; lds_bytes is the dynamic LDS size.
 hipError_t launch_sample(int integrand, int dim, int blocks, int threads, size_t lds_bytes,
@@ -57,5 +61,59 @@ hipError_t launch_finalize(const double *partials, int blocks, int nhist, int hi
                            int with_hist, uint32_t *flag, double *out, hipStream_t stream);
 
 hipError_t launch_clear_flag(uint32_t *flag, hipStream_t stream);
+
+// ---- batched sampling: many integrals in one persistent launch ----
+
+// One integral of a batch.  a carries its constants, grid and table pointers,
+// lattice, iteration and whether this pass collects bin contributions (its
+// trace, partials and stride fields are unused).  out holds [I, var, flag, 0,
+// d*nb bin contributions] of the integral's latest pass; when refine is set,
+// the grid is adjusted on the device from that histogram after the pass.
+struct BatchItem {
+    SampleArgs a;
+    double *grid;     // the integral's grid (a.grid, writable)
+    double *out;
+    double alpha;
+    int32_t refine;
+    int32_t pad;
+};
+
+// A contiguous range of one integral's sub-cubes, processed by one workgroup.
+struct BatchSegment {
+    int32_t item;       // integral (index into the items array)
+    int32_t pad;
+    int64_t t0, t1;     // sub-cubes [t0, t1)
+    int64_t hist_off;   // doubles into the segment-histogram buffer (collecting items)
+};
+
+// The device arrays of one batched step.  Workgroup w processes segments
+// [wg_first[w], wg_first[w+1]); an integral's segments are contiguous, in
+// [item_first[i], item_first[i+1]).
+struct BatchArgs {
+    const BatchItem *items;
+    const BatchSegment *segs;
+    const int32_t *wg_first;
+    const int32_t *item_first;
+    double *seg_tot;          // 4 doubles per segment
+    double *seg_hist;
+    uint32_t *flags;          // per item, zero before the step
+    double *res;              // per item: I, var, flag, 0 (packed for one read-back)
+    int32_t n_items;
+};
+
+// Launches the batched sampling kernel of one precision over the segments of
+// its workgroups (wg_first points at this launch's workgroup table).
+hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
+                        const BatchArgs &args);
+const void *batch_kernel(bool fp32);
+// Merges every integral's segments in order into its out and res and clears its flag.
+hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream);
+// Adjust-Bin-Bounds on the device for n_axes (integral, axis) pairs
+// (axis_item[2a], axis_item[2a+1]): reads the integral's histogram from its out
+// and its boundaries from a.grid, writes the new ones to next_grid[integral].
+hipError_t launch_batch_refine(const BatchItem *items, const int32_t *axis_item,
+                               double *const *next_grid, int n_axes, int max_nb,
+                               hipStream_t stream);
+const void *batch_refine_symbol();
 
 }  // namespace mcubes

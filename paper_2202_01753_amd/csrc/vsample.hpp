@@ -6,7 +6,8 @@
 // (seed; iteration, sub-cube, sample) rather than by thread, the mapping of
 // sub-cubes to lanes does not change any sample point.
 //
-// Per sample (all FP64, no implicit contraction; fma only where written):
+// Per sample (FP64, or FP32 for the map and the integrand in the FP32-eval
+// path; no implicit contraction, fma only where written):
 //   Philox4x32-10 blocks -> 52-bit uniforms -> stratified coordinate in bins
 //   -> bin index, boundary and width from the LDS copy of the grid -> point
 //   and Jacobian -> integrand -> I_k = f J / (m p) -> shifted per-cube sums
@@ -16,6 +17,8 @@
 // workgroup reduction, then the totals and the LDS histogram go to this
 // workgroup's slot of the partials array for the finalize kernel.
 #pragma once
+
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -51,72 +54,103 @@ __device__ __forceinline__ double uniform53(uint32_t whi, uint32_t wlo) {
     return __hiloint2double((int)hi, (int)lo) - 0x1.fffffffffffffp-1;
 }
 
+// ---------------------------------------------------------------- FP32-eval helpers
+
+// (2 (w >> 9) + 1) 2^-24: the float with exponent 0 and mantissa w >> 9 is
+// 1 + (w >> 9) 2^-23; subtracting 1 - 2^-24 is exact (Sterbenz).
+__device__ __forceinline__ float uniform24(uint32_t w) {
+    return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
+}
+
+// Arithmetic of the evaluation precision R (double for the FP64 path, float
+// for FP32 evaluation): each is a single correctly rounded IEEE operation.
+__device__ __forceinline__ double rfma(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float rfma(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double rfloor(double a) { return floor(a); }
+__device__ __forceinline__ float rfloor(float a) { return floorf(a); }
+__device__ __forceinline__ double rmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float rmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double rmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float rmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double rexp(double a) { return exp(a); }
+__device__ __forceinline__ float rexp(float a) { return expf(a); }
+
 // ---------------------------------------------------------------- integrands
 
-__device__ __forceinline__ double lerp(double a, double b, double t) {
-    return __fma_rn(t, b - a, a);
+template <typename R>
+__device__ __forceinline__ R lerp(R a, R b, R t) {
+    return rfma(t, b - a, a);
 }
 
 // Bilinear interpolation in one 256x256 table, node (a,b) at (a/255, b/255),
 // the edge cell extended outside the unit square.
-__device__ __forceinline__ double bilinear(const double *__restrict__ T, double x, double y) {
-    const double ux = x * 255.0, uy = y * 255.0;
-    const double fa = fmin(fmax(floor(ux), 0.0), 254.0);
-    const double fb = fmin(fmax(floor(uy), 0.0), 254.0);
-    const double tx = ux - fa, ty = uy - fb;
+template <typename R>
+__device__ __forceinline__ R bilinear(const R *__restrict__ T, R x, R y) {
+    const R ux = x * R(255), uy = y * R(255);
+    const R fa = rmin(rmax(rfloor(ux), R(0)), R(254));
+    const R fb = rmin(rmax(rfloor(uy), R(0)), R(254));
+    const R tx = ux - fa, ty = uy - fb;
     const int cell = (int)fa * kTableN + (int)fb;
-    const double t00 = T[cell];
-    const double t01 = T[cell + 1];
-    const double t10 = T[cell + kTableN];
-    const double t11 = T[cell + kTableN + 1];
+    const R t00 = T[cell];
+    const R t01 = T[cell + 1];
+    const R t10 = T[cell + kTableN];
+    const R t11 = T[cell + kTableN + 1];
     return lerp(lerp(t00, t10, tx), lerp(t01, t11, tx), ty);
 }
 
-template <int D>
-__device__ __forceinline__ double gauss_product(const double *sC, const double (&x)[D]) {
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const double t = (x[j] - sC[kConstStride * j + 3]) * sC[kConstStride * j + 4];
-        acc = __fma_rn(t, t, acc);
-    }
-    return exp(-acc);
-}
+// The integrand, accumulated axis by axis in ascending order so that the
+// point itself need not stay in registers:
+//   Gaussian product  acc = sum_j t_j^2 by fma, t_j = (x_j - c_j) * (1/w_j); f = exp(-acc)
+//   corner peak       S = 1 + sum_j a_j x_j by fma; f = 1 / S^(D+1), the power by
+//                     left-to-right binary powering, one correctly rounded division
+//   tables            the Gaussian product times T1(x_1, x_2) times T2(x_3, x_4)
+template <int F, int D, typename R>
+struct Integrand {
+    R acc;
+    R x0, x1, x2, x3;  // table coordinates (tables only)
 
-// S^(D+1) by left-to-right binary powering, then one correctly rounded division.
-template <int D>
-__device__ __forceinline__ double corner_peak(const double *sC, const double (&x)[D]) {
-    double S = 1.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) S = __fma_rn(sC[kConstStride * j + 3], x[j], S);
-    constexpr unsigned e = (unsigned)(D + 1);
-    constexpr int top = 31 - __builtin_clz(e);
-    double pw = S;
-#pragma unroll
-    for (int bit = top - 1; bit >= 0; --bit) {
-        pw = pw * pw;
-        if ((e >> bit) & 1u) pw = pw * S;
-    }
-    return 1.0 / pw;
-}
+    __device__ __forceinline__ Integrand() : acc(F == 2 ? R(1) : R(0)), x0(0), x1(0), x2(0), x3(0) {}
 
-template <int F, int D>
-__device__ __forceinline__ double integrand(const SampleArgs &a, const double *sC,
-                                            const double (&x)[D]) {
-    if constexpr (F == 0) {
-        return a.cval;
-    } else if constexpr (F == 1) {
-        return gauss_product<D>(sC, x);
-    } else if constexpr (F == 2) {
-        return corner_peak<D>(sC, x);
-    } else {
-        static_assert(D >= 4, "table integrand needs four axes");
-        const double G = gauss_product<D>(sC, x);
-        const double T1 = bilinear(a.tables, x[0], x[1]);
-        const double T2 = bilinear(a.tables + kTableN * kTableN, x[2], x[3]);
-        return (G * T1) * T2;
+    __device__ __forceinline__ void axis(int j, R xj, const R *cj) {
+        if constexpr (F == 1 || F == 3) {
+            const R t = (xj - cj[3]) * cj[4];
+            acc = rfma(t, t, acc);
+        } else if constexpr (F == 2) {
+            acc = rfma(cj[3], xj, acc);
+        }
+        if constexpr (F == 3) {
+            if (j == 0) x0 = xj;
+            if (j == 1) x1 = xj;
+            if (j == 2) x2 = xj;
+            if (j == 3) x3 = xj;
+        }
     }
-}
+
+    __device__ __forceinline__ R value(const SampleArgs &a) const {
+        if constexpr (F == 0) {
+            return R(a.cval);
+        } else if constexpr (F == 1) {
+            return rexp(-acc);
+        } else if constexpr (F == 2) {
+            constexpr unsigned e = (unsigned)(D + 1);
+            constexpr int top = 31 - __builtin_clz(e);
+            R pw = acc;
+#pragma unroll
+            for (int bit = top - 1; bit >= 0; --bit) {
+                pw = pw * pw;
+                if ((e >> bit) & 1u) pw = pw * acc;
+            }
+            return R(1) / pw;
+        } else {
+            static_assert(D >= 4, "table integrand needs four axes");
+            const R *T = static_cast<const R *>(a.tables);
+            const R G = rexp(-acc);
+            const R T1 = bilinear(T, x0, x1);
+            const R T2 = bilinear(T + kTableN * kTableN, x2, x3);
+            return (G * T1) * T2;
+        }
+    }
+};
 
 // ---------------------------------------------------------------- compensated sums
 
@@ -137,142 +171,202 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
     c = (c + c2) + e;
 }
 
-// ---------------------------------------------------------------- the kernel
+// ---------------------------------------------------------------- LDS layout
 
-// TRACE instantiations additionally write per-sample and per-cube records for
-// the sub-cubes [t0, t1); everything else is the same code.
-template <int F, int D, bool TRACE>
-__global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) {
-    extern __shared__ double lds[];
-    __shared__ double wave_tot[kMaxBlock / 64][4];
-    __shared__ uint32_t wave_bad;
+// Per workgroup: per-axis constants (kConstStride values of the evaluation
+// precision per axis), the grid, then (V-Sample only) the d x nb histogram.
+// FP64 keeps each axis's nb+1 boundaries; FP32 keeps per bin its left
+// boundary and width, each rounded once from FP64.
+template <bool F32>
+__host__ __device__ constexpr size_t lds_const_bytes(int d) {
+    return (size_t)kConstStride * d * (F32 ? sizeof(float) : sizeof(double));
+}
+template <bool F32>
+__host__ __device__ constexpr size_t lds_grid_bytes(int d, int nb) {
+    return F32 ? (size_t)d * nb * 2 * sizeof(float) : (size_t)d * (nb + 1) * sizeof(double);
+}
 
-    const int nb = a.nb;
-    const int row = nb + 1;
-    double *sC = lds;                       // D blocks of per-axis constants
-    double *sB = lds + kConstStride * D;    // D rows of nb+1 boundaries
-    double *sH = sB + D * row;              // D rows of nb bin contributions
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+// ---------------------------------------------------------------- building blocks
 
-    for (int i = tid; i < kConstStride * D; i += nthr) sC[i] = a.consts[i];
-    for (int i = tid; i < D * row; i += nthr) sB[i] = a.grid[i];
+template <bool F32>
+using real_t = typename std::conditional<F32, float, double>::type;
+
+// The workgroup's LDS regions for an integral of dimension d with nb bins.
+template <bool F32>
+struct LdsView {
+    real_t<F32> *consts;
+    real_t<F32> *grid;
+    double *hist;
+    __device__ LdsView(double *lds, int d, int nb) {
+        char *base = reinterpret_cast<char *>(lds);
+        consts = reinterpret_cast<real_t<F32> *>(base);
+        grid = reinterpret_cast<real_t<F32> *>(base + lds_const_bytes<F32>(d));
+        hist = reinterpret_cast<double *>(base + lds_const_bytes<F32>(d) + lds_grid_bytes<F32>(d, nb));
+    }
+};
+
+// Copies the integral's constants and grid into LDS and clears the histogram.
+// Callers synchronise the workgroup afterwards.
+template <int D, bool F32>
+__device__ __forceinline__ void load_lds(const SampleArgs &a, const LdsView<F32> &v) {
+    using R = real_t<F32>;
+    const int nb = a.nb, row = nb + 1, tid = threadIdx.x, nthr = blockDim.x;
+    const R *gconst = static_cast<const R *>(a.consts);
+    for (int i = tid; i < kConstStride * D; i += nthr) v.consts[i] = gconst[i];
+    if constexpr (F32) {
+        for (int i = tid; i < D * nb; i += nthr) {
+            const int j = i / nb, b = i - j * nb;
+            const double *B = a.grid + j * row + b;
+            v.grid[2 * i] = (float)B[0];
+            v.grid[2 * i + 1] = (float)(B[1] - B[0]);
+        }
+    } else {
+        for (int i = tid; i < D * row; i += nthr) v.grid[i] = a.grid[i];
+    }
     if (a.hist)
-        for (int i = tid; i < D * nb; i += nthr) sH[i] = 0.0;
-    if (tid == 0) wave_bad = 0u;
-    __syncthreads();
+        for (int i = tid; i < D * nb; i += nthr) v.hist[i] = 0.0;
+}
 
-    constexpr int NBLK = (D + 1) / 2;
+// All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
+// contributions to the LDS histogram when collecting them, and records the
+// cube in the trace when tracing.
+template <int F, int D, bool TRACE, bool F32>
+__device__ __forceinline__ void cube_pass(const SampleArgs &a, const LdsView<F32> &v, uint64_t t,
+                                          const uint32_t (&dig)[D], double &It, double &vt,
+                                          bool &bad) {
+    using R = real_t<F32>;
+    constexpr int NBLK = (D + 1) / 2;                      // blocks in the counter layout
+    constexpr int NUSED = F32 ? (D + 3) / 4 : NBLK;        // blocks this precision needs
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
-    const uint32_t g = (uint32_t)a.g;
+    const int nb = a.nb, row = nb + 1, rec = 3 * D + 2;
+    const R s = R(F32 ? a.s32 : a.s);
+    const R last = R(nb - 1);
+    const R *sC = v.consts;
+    const R *sG = v.grid;
+    double *sH = v.hist;
 
-    uint64_t t = (uint64_t)blockIdx.x * (uint64_t)nthr + (uint64_t)tid;
-    uint32_t dig[D];
-    {
-        uint64_t rest = t;
+    R cd[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) cd[j] = R(dig[j]);
+    const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
+    const bool traced = TRACE && (int64_t)t >= a.t0 && (int64_t)t < a.t1;
+
+    double I0 = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int k = 0; k < a.p; ++k) {
+        uint32_t w[4 * NUSED];
+#pragma unroll
+        for (int b = 0; b < NUSED; ++b) {
+            uint32_t x0 = (uint32_t)(k * NBLK + b), x1 = a.iter, x2 = tlo, x3 = thi;
+            philox4x32_10(x0, x1, x2, x3, k0, k1);
+            w[4 * b] = x0;
+            w[4 * b + 1] = x1;
+            w[4 * b + 2] = x2;
+            w[4 * b + 3] = x3;
+        }
+        Integrand<F, D, R> fx;
+        int bin[D];
+        R J = R(1);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            dig[j] = (uint32_t)(rest % (uint64_t)g);
-            rest /= (uint64_t)g;
-        }
-    }
-
-    double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
-    bool bad = false;
-    const int rec = 3 * D + 2;
-
-    while (t < (uint64_t)a.m) {
-        double cd[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) cd[j] = (double)dig[j];
-        const uint32_t tlo = (uint32_t)t, thi = (uint32_t)(t >> 32);
-        const bool traced = TRACE && (int64_t)t >= a.t0 && (int64_t)t < a.t1;
-
-        double I0 = 0.0, S1 = 0.0, S2 = 0.0;
-        for (int k = 0; k < a.p; ++k) {
-            uint32_t w[4 * NBLK];
-#pragma unroll
-            for (int b = 0; b < NBLK; ++b) {
-                uint32_t x0 = (uint32_t)(k * NBLK + b), x1 = a.iter, x2 = tlo, x3 = thi;
-                philox4x32_10(x0, x1, x2, x3, k0, k1);
-                w[4 * b] = x0;
-                w[4 * b + 1] = x1;
-                w[4 * b + 2] = x2;
-                w[4 * b + 3] = x3;
-            }
-            double x[D];
-            int bin[D];
-            double J = 1.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const double u = uniform53(w[j], w[D + j]);
-                const double z = (cd[j] + u) * a.s;
-                // bin index, clamped to the last bin with fraction 1 there: once
-                // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
-                // gives exactly 1; otherwise z - floor(z) < 1 is exact.
-                const double fz = fmin(floor(z), a.nb_minus1);
-                const int i = (int)fz;
-                const double frac = fmin(z - fz, 1.0);
-                const double *B = sB + j * row + i;
-                const double left = B[0];
-                const double width = B[1] - left;
-                const double xu = __fma_rn(frac, width, left);
-                const double *cj = sC + kConstStride * j;
-                x[j] = __fma_rn(cj[1], xu, cj[0]);
-                J = J * (width * cj[2]);
-                bin[j] = i;
-                if (traced) {
-                    double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
-                    r[j] = u;
-                    r[D + j] = (double)i;
-                    r[2 * D + j] = x[j];
-                }
-            }
-            const double f = integrand<F, D>(a, sC, x);
-            bad |= !isfinite(f);
-            const double Fv = f * J;
-            const double Ik = Fv * a.inv;
-            if (k == 0) {
-                I0 = Ik;
+            R u;
+            if constexpr (F32) u = uniform24(w[j]);
+            else u = uniform53(w[j], w[D + j]);
+            const R z = (cd[j] + u) * s;
+            // bin index, clamped to the last bin with fraction 1 there: once
+            // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
+            // gives exactly 1; otherwise z - floor(z) < 1 is exact.
+            const R fz = rmin(rfloor(z), last);
+            const int i = (int)fz;
+            const R frac = rmin(z - fz, R(1));
+            R left, width;
+            if constexpr (F32) {
+                const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
+                left = cell.x;
+                width = cell.y;
             } else {
-                const double dev = Ik - I0;
-                S1 = S1 + dev;
-                S2 = __fma_rn(dev, dev, S2);
+                const R *B = sG + j * row + i;
+                left = B[0];
+                width = B[1] - left;
             }
-            if (a.hist) {
-                const double sq = Ik * Ik;
-#pragma unroll
-                for (int j = 0; j < D; ++j) atomicAdd(&sH[j * nb + bin[j]], sq);
-            }
+            const R xu = rfma(frac, width, left);
+            const R *cj = sC + kConstStride * j;
+            const R xj = rfma(cj[1], xu, cj[0]);
+            J = J * (width * cj[2]);
+            bin[j] = i;
+            fx.axis(j, xj, cj);
             if (traced) {
                 double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
-                r[3 * D] = J;
-                r[3 * D + 1] = f;
+                r[j] = (double)u;
+                r[D + j] = (double)i;
+                r[2 * D + j] = (double)xj;
             }
         }
-        const double It = __fma_rn(a.pd, I0, S1);
-        const double num = __fma_rn(-S1, S1, a.pd * S2);
-        double vt = num * a.inv_pm1;
-        if (vt < 0.0) vt = 0.0;
-        two_sum_add(sI, cI, It);
-        two_sum_add(sV, cV, vt);
-        if (traced) {
-            double *r = a.trace + (uint64_t)(a.t1 - a.t0) * (uint64_t)a.p * rec + (t - a.t0) * 2;
-            r[0] = It;
-            r[1] = vt;
+        const R f = fx.value(a);
+        bad |= !isfinite(f);
+        const double Fv = (double)f * (double)J;
+        const double Ik = Fv * a.inv;
+        if (k == 0) {
+            I0 = Ik;
+        } else {
+            const double dev = Ik - I0;
+            S1 = S1 + dev;
+            S2 = __fma_rn(dev, dev, S2);
         }
-        // next sub-cube of this lane: t += stride, digit by digit
-        t += (uint64_t)a.stride;
-        uint32_t carry = 0;
+        if (a.hist) {
+            const double sq = Ik * Ik;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const uint32_t v = dig[j] + (uint32_t)a.sdig[j] + carry;  // < 2g + 1 <= 2^31 + 1
-            carry = v >= g ? 1u : 0u;
-            dig[j] = carry ? v - g : v;
+            for (int j = 0; j < D; ++j) atomicAdd(&sH[j * nb + bin[j]], sq);
+        }
+        if (traced) {
+            double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
+            r[3 * D] = (double)J;
+            r[3 * D + 1] = (double)f;
         }
     }
+    It = __fma_rn(a.pd, I0, S1);
+    const double num = __fma_rn(-S1, S1, a.pd * S2);
+    vt = num * a.inv_pm1;
+    if (vt < 0.0) vt = 0.0;
+    if (traced) {
+        double *r = a.trace + (uint64_t)(a.t1 - a.t0) * (uint64_t)a.p * rec + (t - a.t0) * 2;
+        r[0] = It;
+        r[1] = vt;
+    }
+}
 
-    // lane -> wave: butterfly with compensated merges (every lane ends equal)
+// dig += step digit by digit in base g (the carry out of the top digit is
+// dropped: the caller's cube index tells whether the lane is done).
+template <int D>
+__device__ __forceinline__ void odometer_add(uint32_t (&dig)[D], const int32_t *step, uint32_t g) {
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const uint32_t v = dig[j] + (uint32_t)step[j] + carry;  // < 2g + 1 <= 2^31 + 1
+        carry = v >= g ? 1u : 0u;
+        dig[j] = carry ? v - g : v;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void digits_of(uint64_t t, uint32_t g, uint32_t (&dig)[D]) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        dig[j] = (uint32_t)(t % (uint64_t)g);
+        t /= (uint64_t)g;
+    }
+}
+
+// Workgroup reduction of the lanes' compensated (I, var) sums: a butterfly in
+// each wavefront, then the wavefronts in order.  Thread 0 writes the four
+// doubles (sum and compensation of I and var) to out and raises *flag if any
+// lane saw a non-finite integrand value.  Ends with a workgroup barrier.
+__device__ __forceinline__ void block_totals(double sI, double cI, double sV, double cV, bool bad,
+                                             double *out, uint32_t *flag) {
+    __shared__ double wave_tot[kMaxBlock / 64][4];
+    __shared__ uint32_t wave_bad;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    if (tid == 0) wave_bad = 0u;
+    __syncthreads();
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const double s2 = __shfl_xor(sI, off, 64), c2 = __shfl_xor(cI, off, 64);
@@ -289,36 +383,70 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     }
     if (__any(bad) && (tid & 63) == 0) atomicOr(&wave_bad, 1u);
     __syncthreads();
-
-    double *part = a.partials;
     if (tid == 0) {
         double s0 = wave_tot[0][0], c0 = wave_tot[0][1], v0 = wave_tot[0][2], e0 = wave_tot[0][3];
         for (int wv = 1; wv < nthr / 64; ++wv) {
             two_sum_merge(s0, c0, wave_tot[wv][0], wave_tot[wv][1]);
             two_sum_merge(v0, e0, wave_tot[wv][2], wave_tot[wv][3]);
         }
-        double *o = part + 4 * (size_t)blockIdx.x;
-        o[0] = s0;
-        o[1] = c0;
-        o[2] = v0;
-        o[3] = e0;
-        if (wave_bad) atomicOr(a.flag, 1u);
+        out[0] = s0;
+        out[1] = c0;
+        out[2] = v0;
+        out[3] = e0;
+        if (wave_bad) atomicOr(flag, 1u);
     }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- the kernel
+
+// One integral: persistent workgroups stride through all m sub-cubes.
+// TRACE instantiations additionally write per-sample and per-cube records for
+// the sub-cubes [t0, t1); F32 instantiations evaluate the map and the
+// integrand in single precision.  Everything from I_k on is FP64 in both.
+template <int F, int D, bool TRACE, bool F32>
+__global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) {
+    extern __shared__ double lds[];
+    const LdsView<F32> v(lds, D, a.nb);
+    load_lds<D, F32>(a, v);
+    __syncthreads();
+
+    uint64_t t = (uint64_t)blockIdx.x * (uint64_t)blockDim.x + (uint64_t)threadIdx.x;
+    uint32_t dig[D];
+    digits_of<D>(t, (uint32_t)a.g, dig);
+    double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
+    bool bad = false;
+    while (t < (uint64_t)a.m) {
+        double It, vt;
+        cube_pass<F, D, TRACE, F32>(a, v, t, dig, It, vt, bad);
+        two_sum_add(sI, cI, It);
+        two_sum_add(sV, cV, vt);
+        // next sub-cube of this lane: t += stride, digit by digit
+        t += (uint64_t)a.stride;
+        odometer_add<D>(dig, a.sdig, (uint32_t)a.g);
+    }
+    block_totals(sI, cI, sV, cV, bad, a.partials + 4 * (size_t)blockIdx.x, a.flag);
     if (a.hist) {
-        double *ph = part + 4 * (size_t)gridDim.x + (size_t)blockIdx.x * a.hist_stride;
-        for (int i = tid; i < D * nb; i += nthr) ph[i] = sH[i];
+        double *ph = a.partials + 4 * (size_t)gridDim.x + (size_t)blockIdx.x * a.hist_stride;
+        for (int i = threadIdx.x; i < D * a.nb; i += blockDim.x) ph[i] = v.hist[i];
     }
 }
 
 template <int F, int D>
 hipError_t launch_sample_fd(int blocks, int threads, size_t lds_bytes, hipStream_t stream,
                             const SampleArgs &args) {
-    if (args.trace)
-        hipLaunchKernelGGL((vsample_kernel<F, D, true>), dim3(blocks), dim3(threads), lds_bytes,
-                           stream, args);
-    else
-        hipLaunchKernelGGL((vsample_kernel<F, D, false>), dim3(blocks), dim3(threads), lds_bytes,
-                           stream, args);
+    const dim3 grid(blocks), block(threads);
+    if (args.fp32) {
+        if (args.trace)
+            hipLaunchKernelGGL((vsample_kernel<F, D, true, true>), grid, block, lds_bytes, stream, args);
+        else
+            hipLaunchKernelGGL((vsample_kernel<F, D, false, true>), grid, block, lds_bytes, stream, args);
+    } else {
+        if (args.trace)
+            hipLaunchKernelGGL((vsample_kernel<F, D, true, false>), grid, block, lds_bytes, stream, args);
+        else
+            hipLaunchKernelGGL((vsample_kernel<F, D, false, false>), grid, block, lds_bytes, stream, args);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,221 @@
+// Batched V-Sample: the sampling passes of many independent integrals (any
+// mix of integrand, dimension and bin count) in one persistent launch.  The
+// host splits the active integrals' sub-cubes into contiguous segments of
+// roughly equal work and gives each workgroup a run of consecutive segments;
+// for each segment the workgroup loads that integral's constants and grid
+// into LDS, samples the segment's cubes with the same per-cube code as the
+// single-integral kernel, and writes the segment's totals and histogram.
+// A second kernel merges every integral's segments in order, and a third
+// adjusts the grids of the integrals still in their adjusting iterations, on
+// the device, so that grids and histograms never leave it.
+#include "vsample.hpp"
+
+namespace mcubes {
+
+namespace {
+
+template <int F, int D, bool F32>
+__device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegment &sg, int si,
+                                            double *lds, const BatchArgs &B) {
+    const LdsView<F32> v(lds, D, a.nb);
+    load_lds<D, F32>(a, v);
+    __syncthreads();
+    const uint32_t g = (uint32_t)a.g;
+    int32_t step[D];  // blockDim in base g
+    {
+        uint32_t sd[D];
+        digits_of<D>((uint64_t)blockDim.x, g, sd);
+#pragma unroll
+        for (int j = 0; j < D; ++j) step[j] = (int32_t)sd[j];
+    }
+    uint64_t t = (uint64_t)sg.t0 + threadIdx.x;
+    uint32_t dig[D];
+    digits_of<D>(t, g, dig);
+    double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
+    bool bad = false;
+    while (t < (uint64_t)sg.t1) {
+        double It, vt;
+        cube_pass<F, D, false, F32>(a, v, t, dig, It, vt, bad);
+        two_sum_add(sI, cI, It);
+        two_sum_add(sV, cV, vt);
+        t += blockDim.x;
+        odometer_add<D>(dig, step, g);
+    }
+    block_totals(sI, cI, sV, cV, bad, B.seg_tot + 4 * (size_t)si, B.flags + sg.item);
+    if (a.hist) {
+        double *dst = B.seg_hist + sg.hist_off;
+        for (int i = threadIdx.x; i < D * a.nb; i += blockDim.x) dst[i] = v.hist[i];
+    }
+    __syncthreads();  // LDS is reused by the next segment
+}
+
+#define MC_CASE(F, D) \
+    case (F) * 32 + (D): run_segment<F, D, F32>(a, sg, si, lds, B); break;
+#define MC_CASES_1_10(F)                                                                           \
+    MC_CASE(F, 1) MC_CASE(F, 2) MC_CASE(F, 3) MC_CASE(F, 4) MC_CASE(F, 5) MC_CASE(F, 6)           \
+    MC_CASE(F, 7) MC_CASE(F, 8) MC_CASE(F, 9) MC_CASE(F, 10)
+
+// Register budget: every (integrand, dimension) case shares the kernel's
+// allocation, so the largest case sets it.
+template <bool F32>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3)))
+vsample_batch_kernel(const BatchArgs B) {
+    extern __shared__ double lds[];
+    const int first = B.wg_first[blockIdx.x], last = B.wg_first[blockIdx.x + 1];
+    for (int si = first; si < last; ++si) {
+        const BatchSegment sg = B.segs[si];
+        const SampleArgs &a = B.items[sg.item].a;
+        switch (a.kind) {
+            MC_CASES_1_10(0)
+            MC_CASES_1_10(1)
+            MC_CASES_1_10(2)
+            MC_CASE(3, 4) MC_CASE(3, 5) MC_CASE(3, 6) MC_CASE(3, 7) MC_CASE(3, 8) MC_CASE(3, 9)
+            MC_CASE(3, 10)
+            default: break;
+        }
+    }
+}
+
+#undef MC_CASES_1_10
+#undef MC_CASE
+
+constexpr int kFinThreads = 256;
+
+// One block per integral: totals and (collecting integrals) each bin summed
+// over the integral's segments in order, TwoSum-compensated.
+__global__ void __launch_bounds__(kFinThreads) batch_finalize_kernel(const BatchArgs B) {
+    const int item = blockIdx.x;
+    const BatchItem &it = B.items[item];
+    const int s0 = B.item_first[item], s1 = B.item_first[item + 1];
+    double *o = it.out;
+    if (threadIdx.x == 0) {
+        double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
+        for (int s = s0; s < s1; ++s) {
+            const double *q = B.seg_tot + 4 * (size_t)s;
+            two_sum_merge(sI, cI, q[0], q[1]);
+            two_sum_merge(sV, cV, q[2], q[3]);
+        }
+        const double flag = B.flags[item] ? 1.0 : 0.0;
+        o[0] = B.res[4 * item] = sI + cI;
+        o[1] = B.res[4 * item + 1] = sV + cV;
+        o[2] = B.res[4 * item + 2] = flag;
+        o[3] = B.res[4 * item + 3] = 0.0;
+        B.flags[item] = 0u;
+    }
+    if (it.a.hist) {
+        const int nh = (it.a.kind & 31) * it.a.nb;
+        for (int b = threadIdx.x; b < nh; b += kFinThreads) {
+            double s = 0.0, c = 0.0;
+            for (int q = s0; q < s1; ++q) two_sum_merge(s, c, B.seg_hist[B.segs[q].hist_off + b], 0.0);
+            o[4 + b] = s + c;
+        }
+    }
+}
+
+// Adjust-Bin-Bounds on the device, one block per (integral, axis): three-
+// point smoothing and Lepage's damped compression ((1 - s_i/S)/ln(S/s_i))^alpha
+// across the block, the running sums and the equal-share rebinning in order
+// by one lane (the same steps and summation order as the host version; pow
+// and log are the device library's).  Reads the axis's histogram from out
+// and its boundaries from a.grid, writes the new boundaries to next.
+constexpr int kRefThreads = 64;
+
+__global__ void __launch_bounds__(kRefThreads)
+batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *const *next_grid) {
+    extern __shared__ double r[];  // nb doubles
+    const int ax = blockIdx.x;
+    const int item = axis_item[2 * ax], j = axis_item[2 * ax + 1];
+    const BatchItem &it = items[item];
+    const int nb = it.a.nb;
+    const double *C = it.out + 4 + (size_t)j * nb;
+    const double *B = it.a.grid + (size_t)j * (nb + 1);
+    double *Bn = next_grid[item] + (size_t)j * (nb + 1);
+    const double alpha = it.alpha;
+    for (int i = threadIdx.x; i < nb; i += kRefThreads) {
+        double s;
+        if (i == 0) s = (C[0] + C[1]) / 2.0;
+        else if (i == nb - 1) s = (C[nb - 2] + C[nb - 1]) / 2.0;
+        else s = ((C[i - 1] + C[i]) + C[i + 1]) / 3.0;
+        r[i] = s;
+    }
+    __syncthreads();
+    __shared__ double total_s;
+    __shared__ int usable;
+    if (threadIdx.x == 0) {
+        double S = 0.0;
+        for (int i = 0; i < nb; ++i) S = S + r[i];
+        total_s = S;
+        usable = (S > 0.0) && isfinite(S);
+    }
+    __syncthreads();
+    if (!usable) {  // no usable weight: the axis keeps its boundaries
+        for (int i = threadIdx.x; i <= nb; i += kRefThreads) Bn[i] = B[i];
+        return;
+    }
+    const double S = total_s;
+    for (int i = threadIdx.x; i < nb; i += kRefThreads) {
+        const double s = r[i];
+        r[i] = s == 0.0 ? 0.0 : (s == S ? 1.0 : pow((1.0 - s / S) / log(S / s), alpha));
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double R = 0.0;
+    for (int i = 0; i < nb; ++i) R = R + r[i];
+    if (!(R > 0.0)) {
+        for (int i = 0; i <= nb; ++i) Bn[i] = B[i];
+        return;
+    }
+    const double per_bin = R / (double)nb;
+    int src = 0;
+    double acc = 0.0, prev_edge = 0.0;
+    Bn[0] = 0.0;
+    for (int k = 1; k < nb; ++k) {
+        const double goal = (double)k * per_bin;
+        while (src < nb - 1 && acc + r[src] < goal) {
+            acc = acc + r[src];
+            ++src;
+        }
+        double frac = r[src] > 0.0 ? (goal - acc) / r[src] : 0.0;
+        frac = fmin(fmax(frac, 0.0), 1.0);
+        const double edge = __fma_rn(frac, B[src + 1] - B[src], B[src]);
+        prev_edge = fmax(edge, prev_edge);
+        Bn[k] = prev_edge;
+    }
+    Bn[nb] = 1.0;
+}
+
+}  // namespace
+
+hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
+                        const BatchArgs &args) {
+    if (fp32)
+        hipLaunchKernelGGL(vsample_batch_kernel<true>, dim3(blocks), dim3(threads), lds_bytes,
+                           stream, args);
+    else
+        hipLaunchKernelGGL(vsample_batch_kernel<false>, dim3(blocks), dim3(threads), lds_bytes,
+                           stream, args);
+    return hipGetLastError();
+}
+
+const void *batch_kernel(bool fp32) {
+    return fp32 ? reinterpret_cast<const void *>(&vsample_batch_kernel<true>)
+                : reinterpret_cast<const void *>(&vsample_batch_kernel<false>);
+}
+
+hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(args.n_items), dim3(kFinThreads), 0, stream, args);
+    return hipGetLastError();
+}
+
+const void *batch_refine_symbol() { return reinterpret_cast<const void *>(&batch_refine_kernel); }
+
+hipError_t launch_batch_refine(const BatchItem *items, const int32_t *axis_item,
+                               double *const *next_grid, int n_axes, int max_nb,
+                               hipStream_t stream) {
+    if (n_axes == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_refine_kernel, dim3(n_axes), dim3(kRefThreads),
+                       sizeof(double) * (size_t)max_nb, stream, items, axis_item, next_grid);
+    return hipGetLastError();
+}
+
+}  // namespace mcubes

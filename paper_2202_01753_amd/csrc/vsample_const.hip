@@ -26,40 +26,33 @@ hipError_t launch_sample_f0(int dim, int blocks, int threads, size_t lds_bytes,
     }
 }
 
-const void *sample_kernel_f0(int dim, bool trace) {
+template <int F, int D>
+static const void *symbol(bool trace, bool fp32) {
+    if (fp32)
+        return trace ? reinterpret_cast<const void *>(&vsample_kernel<F, D, true, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<F, D, false, true>);
+    return trace ? reinterpret_cast<const void *>(&vsample_kernel<F, D, true, false>)
+                 : reinterpret_cast<const void *>(&vsample_kernel<F, D, false, false>);
+}
+
+const void *sample_kernel_f0(int dim, bool trace, bool fp32) {
     switch (dim) {
-    case 1: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 1, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 1, false>);
-    case 2: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 2, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 2, false>);
-    case 3: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 3, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 3, false>);
-    case 4: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 4, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 4, false>);
-    case 5: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 5, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 5, false>);
-    case 6: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 6, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 6, false>);
-    case 7: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 7, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 7, false>);
-    case 8: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 8, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 8, false>);
-    case 9: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 9, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 9, false>);
-    case 10: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 10, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 10, false>);
-    case 11: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 11, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 11, false>);
-    case 12: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 12, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 12, false>);
-    case 13: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 13, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 13, false>);
-    case 14: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 14, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 14, false>);
-    case 15: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 15, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 15, false>);
-    case 16: return trace ? reinterpret_cast<const void *>(&vsample_kernel<0, 16, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<0, 16, false>);
+    case 1: return symbol<0, 1>(trace, fp32);
+    case 2: return symbol<0, 2>(trace, fp32);
+    case 3: return symbol<0, 3>(trace, fp32);
+    case 4: return symbol<0, 4>(trace, fp32);
+    case 5: return symbol<0, 5>(trace, fp32);
+    case 6: return symbol<0, 6>(trace, fp32);
+    case 7: return symbol<0, 7>(trace, fp32);
+    case 8: return symbol<0, 8>(trace, fp32);
+    case 9: return symbol<0, 9>(trace, fp32);
+    case 10: return symbol<0, 10>(trace, fp32);
+    case 11: return symbol<0, 11>(trace, fp32);
+    case 12: return symbol<0, 12>(trace, fp32);
+    case 13: return symbol<0, 13>(trace, fp32);
+    case 14: return symbol<0, 14>(trace, fp32);
+    case 15: return symbol<0, 15>(trace, fp32);
+    case 16: return symbol<0, 16>(trace, fp32);
     default: return nullptr;
     }
 }

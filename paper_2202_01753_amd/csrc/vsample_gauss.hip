@@ -26,40 +26,33 @@ hipError_t launch_sample_f1(int dim, int blocks, int threads, size_t lds_bytes,
     }
 }
 
-const void *sample_kernel_f1(int dim, bool trace) {
+template <int F, int D>
+static const void *symbol(bool trace, bool fp32) {
+    if (fp32)
+        return trace ? reinterpret_cast<const void *>(&vsample_kernel<F, D, true, true>)
+                     : reinterpret_cast<const void *>(&vsample_kernel<F, D, false, true>);
+    return trace ? reinterpret_cast<const void *>(&vsample_kernel<F, D, true, false>)
+                 : reinterpret_cast<const void *>(&vsample_kernel<F, D, false, false>);
+}
+
+const void *sample_kernel_f1(int dim, bool trace, bool fp32) {
     switch (dim) {
-    case 1: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 1, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 1, false>);
-    case 2: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 2, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 2, false>);
-    case 3: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 3, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 3, false>);
-    case 4: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 4, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 4, false>);
-    case 5: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 5, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 5, false>);
-    case 6: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 6, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 6, false>);
-    case 7: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 7, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 7, false>);
-    case 8: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 8, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 8, false>);
-    case 9: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 9, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 9, false>);
-    case 10: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 10, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 10, false>);
-    case 11: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 11, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 11, false>);
-    case 12: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 12, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 12, false>);
-    case 13: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 13, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 13, false>);
-    case 14: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 14, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 14, false>);
-    case 15: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 15, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 15, false>);
-    case 16: return trace ? reinterpret_cast<const void *>(&vsample_kernel<1, 16, true>)
-                     : reinterpret_cast<const void *>(&vsample_kernel<1, 16, false>);
+    case 1: return symbol<1, 1>(trace, fp32);
+    case 2: return symbol<1, 2>(trace, fp32);
+    case 3: return symbol<1, 3>(trace, fp32);
+    case 4: return symbol<1, 4>(trace, fp32);
+    case 5: return symbol<1, 5>(trace, fp32);
+    case 6: return symbol<1, 6>(trace, fp32);
+    case 7: return symbol<1, 7>(trace, fp32);
+    case 8: return symbol<1, 8>(trace, fp32);
+    case 9: return symbol<1, 9>(trace, fp32);
+    case 10: return symbol<1, 10>(trace, fp32);
+    case 11: return symbol<1, 11>(trace, fp32);
+    case 12: return symbol<1, 12>(trace, fp32);
+    case 13: return symbol<1, 13>(trace, fp32);
+    case 14: return symbol<1, 14>(trace, fp32);
+    case 15: return symbol<1, 15>(trace, fp32);
+    case 16: return symbol<1, 16>(trace, fp32);
     default: return nullptr;
     }
 }

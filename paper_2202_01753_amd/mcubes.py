@@ -20,9 +20,13 @@ LIBRARY = os.path.join(PKG, "libmcubes.so")
 
 OK, EINVAL, EWORKSPACE, ENONFINITE, EDEVICE = 0, 1, 2, 3, 4
 INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_init_grid", "mc_weighted_estimate",
-           "mc_integrate")
+           "mc_integrate", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
+           "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_release",
+           "mc_server_stats", "mc_server_destroy")
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
 class MCubesError(RuntimeError):
@@ -59,6 +63,11 @@ class Result(C.Structure):
                 ("iterations", C.c_int32), ("converged", C.c_int32), ("calls", C.c_int64)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("max_active", C.c_int32), ("sample_ms", C.c_double),
+                ("step_ms", C.c_double), ("calls", C.c_int64)]
+
+
 class Timing(C.Structure):
     _fields_ = [("sample_ms", C.c_double), ("finalize_ms", C.c_double), ("launches", C.c_int32),
                 ("blocks", C.c_int32), ("threads", C.c_int32), ("lds_bytes", C.c_int32)]
@@ -91,6 +100,17 @@ def lib() -> C.CDLL:
             "mc_weighted_estimate": ([C.c_int32, dp, dp, dp], C.c_int32),
             "mc_integrate": ([P, vp, sz, vp, C.POINTER(Result), dp, dp, C.POINTER(Timing)],
                              C.c_int32),
+            "mc_batch_workspace_bytes": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
+            "mc_batch_integrate": ([P, C.c_int32, vp, sz, vp, C.POINTER(Result),
+                                    C.POINTER(C.c_int32), C.POINTER(BatchStats)], C.c_int32),
+            "mc_server_create": ([vp, sz, sz, C.c_int32, vp, C.POINTER(vp)], C.c_int32),
+            "mc_server_submit": ([vp, P, C.POINTER(C.c_int64)], C.c_int32),
+            "mc_server_step": ([vp] + [C.POINTER(C.c_int32)] * 3, C.c_int32),
+            "mc_server_poll": ([vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(Result),
+                                C.POINTER(C.c_int32)], C.c_int32),
+            "mc_server_release": ([vp, C.c_int64], C.c_int32),
+            "mc_server_stats": ([vp, C.POINTER(BatchStats)], C.c_int32),
+            "mc_server_destroy": ([vp], C.c_int32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -131,7 +151,8 @@ class BoundProblem:
             n_params=len(self.params), tables=_dp(self.tables),
             n_tables=0 if self.tables is None else len(self.tables), lo=_dp(self.lo),
             hi=_dp(self.hi), maxcalls=int(prob["maxcalls"]), nbins=int(prob["nbins"]),
-            itmax=int(prob["itmax"]), ita=int(prob.get("ita", prob["itmax"])), precision=0,
+            itmax=int(prob["itmax"]), ita=int(prob.get("ita", prob["itmax"])),
+            precision=PRECISIONS[prob.get("precision", "fp64")],
             alpha=float(prob["alpha"]), tau_rel=float(prob.get("tau_rel", 0.0)),
             seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads))
 
@@ -278,3 +299,103 @@ class Sampler:
             res["strace"] = a[:ns * rec].reshape(ns, rec)
             res["ctrace"] = a[ns * rec:ns * rec + 2 * (t1 - t0)].reshape(t1 - t0, 2)
         return res
+
+
+# ---------------------------------------------------------------- batches and serving
+
+def _problem_array(bps):
+    arr = (Problem * len(bps))()
+    for i, bp in enumerate(bps):
+        arr[i] = bp.s
+    return arr
+
+
+def batch_workspace_bytes(probs) -> int:
+    bps = [BoundProblem(p) for p in probs]
+    n = C.c_size_t()
+    _check(lib().mc_batch_workspace_bytes(_problem_array(bps), len(bps), C.byref(n)),
+           "mc_batch_workspace_bytes")
+    return n.value
+
+
+def batch_integrate(probs, stream=None, ws=None):
+    """Runs the problems together; returns (list of result dicts or MCubesError per
+    integral, BatchStats)."""
+    torch = _torch()
+    bps = [BoundProblem(p) for p in probs]
+    arr = _problem_array(bps)
+    n = len(bps)
+    need = C.c_size_t()
+    _check(lib().mc_batch_workspace_bytes(arr, n, C.byref(need)), "mc_batch_workspace_bytes")
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    res = (Result * n)()
+    sts = (C.c_int32 * n)()
+    stats = BatchStats()
+    _check(lib().mc_batch_integrate(arr, n, C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                    res, sts, C.byref(stats)), "mc_batch_integrate")
+    out = []
+    for i in range(n):
+        if sts[i] != OK:
+            out.append(MCubesError(sts[i], f"integral {i}"))
+        else:
+            r = res[i]
+            out.append({"estimate": r.estimate, "error": r.error, "chi2_dof": r.chi2_dof,
+                        "iterations": r.iterations, "converged": bool(r.converged),
+                        "calls": r.calls})
+    return out, stats
+
+
+class Server:
+    """Continuous-batching server (mc_server_*) on a torch-allocated workspace."""
+
+    def __init__(self, ws_bytes: int, arena_bytes: int, max_active: int = 8192, stream=None):
+        torch = _torch()
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().mc_server_create(C.c_void_p(self.ws.data_ptr()), ws_bytes, arena_bytes,
+                                      max_active, _stream(stream), C.byref(h)), "mc_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, prob) -> int:
+        bp = BoundProblem(prob)
+        rid = C.c_int64()
+        _check(lib().mc_server_submit(self.h, bp.ref, C.byref(rid)), "mc_server_submit")
+        return rid.value
+
+    def step(self):
+        a, q, f = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().mc_server_step(self.h, C.byref(a), C.byref(q), C.byref(f)), "mc_server_step")
+        return a.value, q.value, f.value
+
+    def poll(self, rid: int):
+        st, status = C.c_int32(), C.c_int32()
+        r = Result()
+        _check(lib().mc_server_poll(self.h, rid, C.byref(st), C.byref(r), C.byref(status)),
+               "mc_server_poll")
+        res = None
+        if st.value == REQ_DONE:
+            res = {"estimate": r.estimate, "error": r.error, "chi2_dof": r.chi2_dof,
+                   "iterations": r.iterations, "converged": bool(r.converged), "calls": r.calls}
+        return st.value, res, status.value
+
+    def release(self, rid: int):
+        _check(lib().mc_server_release(self.h, rid), "mc_server_release")
+
+    def stats(self) -> BatchStats:
+        s = BatchStats()
+        _check(lib().mc_server_stats(self.h, C.byref(s)), "mc_server_stats")
+        return s
+
+    def close(self):
+        if self.h:
+            _check(lib().mc_server_destroy(self.h), "mc_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,8 +7,9 @@ both the GPU path and the CPU oracle can be fed from it.
 A problem is a plain dict with the keys ``integrand`` ("const",
 "gauss_product", "corner_peak" or "gauss_tables"), ``params`` (float64),
 ``tables`` (float64 of 2*256*256, or None), ``dim``, ``lo``, ``hi``,
-``maxcalls``, ``nbins``, ``itmax``, ``ita``, ``alpha``, ``tau_rel`` and
-``seed`` (the sampling seed, separate from the parameter seed).
+``maxcalls``, ``nbins``, ``itmax``, ``ita``, ``alpha``, ``tau_rel``,
+``seed`` (the sampling seed, separate from the parameter seed) and
+``precision`` ("fp64", or "fp32" for FP32 evaluation with FP64 accumulation).
 
 Parameter layouts:
   const          [v]
@@ -24,7 +25,7 @@ TABLE_N = 256
 
 
 def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=None, hi=None,
-             ita=None, alpha=1.5, tau_rel=0.0, seed=0):
+             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64"):
     return {
         "integrand": integrand,
         "params": np.ascontiguousarray(params, dtype=np.float64),
@@ -39,6 +40,7 @@ def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=
         "alpha": float(alpha),
         "tau_rel": float(tau_rel),
         "seed": int(seed),
+        "precision": precision,
     }
 
 

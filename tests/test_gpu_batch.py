@@ -1,0 +1,141 @@
+"""GPU tests of the batched launch and the serving loop (through the C ABI).
+
+The bar: each integral's result is the same alone and in the mix, within the
+stated tolerance.  Its samples are identical in both (the random numbers are
+keyed by its own seed, iteration, cube and sample); what can differ is the
+order in which sums are formed (different work splits), which moves grids by
+ulps and estimates by far less than 1e-10 relative."""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+import oracle as O
+from paper_2202_01753_amd import mcubes as M
+from paper_2202_01753_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MIX_TOL = 1e-10
+
+
+def _mix(seed=0, n=14):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        d = int(rng.integers(2, 11))
+        kind = ["gauss_product", "corner_peak", "gauss_tables", "const"][i % 4]
+        if kind == "gauss_tables" and d < 4:
+            d = 4 + i % 3
+        N = int(10 ** rng.uniform(3.5, 5.5))
+        nb = int(rng.integers(20, 200))
+        itmax = int(rng.integers(2, 7))
+        kw = dict(maxcalls=N, nbins=nb, itmax=itmax, seed=100 + i,
+                  precision="fp32" if i % 5 == 4 else "fp64")
+        if kind == "gauss_product":
+            p = W.gauss_product(d, 10 + i, **kw)
+        elif kind == "corner_peak":
+            p = W.corner_peak(d, 10 + i, **kw)
+        elif kind == "gauss_tables":
+            p = W.gauss_tables(d, 10 + i, w_range=(0.1, 0.3), **kw)
+        else:
+            p = W.const(d, 1.5, **kw)
+        if i % 3 == 0:
+            p["ita"] = max(1, itmax - 1)
+        if i % 7 == 3:
+            p["tau_rel"] = 2e-3
+        out.append(p)
+    return out
+
+
+def _close(a, b, tol=MIX_TOL):
+    assert a["iterations"] == b["iterations"], (a, b)
+    assert a["converged"] == b["converged"]
+    assert a["estimate"] == pytest.approx(b["estimate"], rel=tol, abs=1e-300)
+    assert a["error"] == pytest.approx(b["error"], rel=100 * tol, abs=1e-300)
+
+
+def test_batch_alone_vs_mix():
+    probs = _mix()
+    mixed, stats = M.batch_integrate(probs)
+    assert stats.steps == max(r["iterations"] for r in mixed)
+    for i, p in enumerate(probs):
+        alone, _ = M.batch_integrate([p])
+        _close(mixed[i], alone[0])
+
+
+def test_batch_matches_single_integral_path_and_oracle():
+    probs = [W.config_small(seed=4), W.corner_peak(5, 14, maxcalls=100_000, nbins=80, itmax=6, seed=5),
+             W.config_tables(seed=6, maxcalls=300_000, itmax=4),
+             dict(W.corner_peak(3, 2, maxcalls=20_000, nbins=60, itmax=5, seed=8), precision="fp32")]
+    mixed, _ = M.batch_integrate(probs)
+    for i, p in enumerate(probs):
+        single = M.integrate(p)
+        r = {"estimate": single.estimate, "error": single.error, "iterations": single.iterations,
+             "converged": single.converged}
+        _close(mixed[i], r)
+        o = O.integrate(p)
+        assert mixed[i]["estimate"] == pytest.approx(o["estimate"], rel=1e-9 if p.get("precision") == "fp32" else MIX_TOL)
+        assert abs(mixed[i]["estimate"] - CF.exact(p)) < 5 * mixed[i]["error"]
+
+
+def test_batch_first_pass_against_oracle():
+    """One non-adjusting iteration per integral: the batch estimate is the
+    oracle's V-Sample estimate on the uniform grid, to summation order."""
+    probs = []
+    for i, p in enumerate(_mix(seed=3, n=8)):
+        q = dict(p, itmax=1, ita=0, tau_rel=0.0)
+        probs.append(q)
+    mixed, _ = M.batch_integrate(probs)
+    for p, r in zip(probs, mixed):
+        ref = O.vsample(p, 0, O.init_grid(p["dim"], p["nbins"]), hist=False, trace=True)
+        scale = float(np.abs(ref["ctrace"][:, 0]).sum())
+        tol = 1e-6 if p.get("precision") == "fp32" and p["integrand"] not in ("const", "corner_peak") else 1e-12
+        assert abs(r["estimate"] - ref["I"]) <= tol * scale + 1e-300, (p["integrand"], p["dim"])
+
+
+def test_batch_nonfinite_is_isolated():
+    good = W.config_small(seed=1)
+    bad = W.const(3, np.inf, maxcalls=1000, nbins=10, itmax=2, seed=2)
+    res, _ = M.batch_integrate([good, bad, W.corner_peak(4, 1, maxcalls=5000, nbins=30, itmax=3, seed=3)])
+    assert isinstance(res[1], M.MCubesError) and res[1].code == M.ENONFINITE
+    alone, _ = M.batch_integrate([good])
+    _close(res[0], alone[0])
+    assert res[2]["iterations"] == 3
+
+
+def test_batch_rejects_high_dimension():
+    with pytest.raises(M.MCubesError) as e:
+        M.batch_integrate([W.gauss_product(11, 1, maxcalls=10_000, nbins=10, itmax=1)])
+    assert e.value.code == M.EINVAL
+
+
+def test_server_admits_by_memory_and_matches_alone():
+    probs = _mix(seed=7, n=10)
+    assert sum(p["integrand"] == "gauss_tables" for p in probs) >= 2
+    # an arena with room for one integral with FP64 tables (1 MiB) and a few
+    # small ones: the second table integral must wait for the first to finish
+    srv = M.Server(ws_bytes=512 * 2**20, arena_bytes=int(1.5 * 2**20), max_active=64)
+    ids = [srv.submit(p) for p in probs[:6]]
+    seen_queued = False
+    steps = 0
+    while True:
+        a, q, f = srv.step()
+        steps += 1
+        seen_queued |= q > 0
+        if steps == 2:
+            ids += [srv.submit(p) for p in probs[6:]]  # arrivals while others run
+        if a == 0 and q == 0 and steps > 2:
+            break
+        assert steps < 500
+    assert seen_queued
+    for rid, p in zip(ids, probs):
+        st, res, status = srv.poll(rid)
+        assert st == M.REQ_DONE and status == M.OK
+        alone, _ = M.batch_integrate([p])
+        _close(res, alone[0])
+        srv.release(rid)
+    s = srv.stats()
+    assert 0 < s.steps <= steps and s.calls > 0
+    srv.close()
