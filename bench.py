@@ -1,6 +1,7 @@
 """Throughput of the m-Cubes VEGAS sampling path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tables|corner8|gauss8|small]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload tables|corner8|gauss8|small|batch|serve] [--precision fp64|fp32]
 
 One step is one complete m-Cubes run (mc_integrate: every iteration of
 sampling kernel + fixed-order reduction + read-back + host weighting, bin
@@ -23,6 +24,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -74,6 +77,8 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
 
 WORKLOADS = {
     "tables": ("gauss_tables_d6_1e8", lambda W, seed: W.config_tables(seed=seed)),
+    "batch": ("batch_4096_mixed", None),
+    "serve": ("served_poisson_2000_per_s", None),
     "small": ("gauss_product_d2_1e4", lambda W, seed: W.config_small(seed=seed)),
     "corner8": ("corner_peak_d8_1e9", lambda W, seed: W.config_corner8(seed=seed)),
     "gauss8": ("gauss_product_d8_w0.01_1e9", lambda W, seed: W.config_gauss8(seed=seed)),
@@ -101,6 +106,106 @@ def cpu_baseline(prob, target_s: float = 12.0):
                       f"sub-cubes [0, {n2}) of {m} = {n2 * p} samples, {dt:.1f} s single-threaded"}
 
 
+def _base_line(args, name, value, ms_per_step, dtype, config):
+    return {"metric": "integrand samples/sec/GPU", "value": value, "unit": "samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": dict({"workload": name}, **config)}
+
+
+def bench_batch(args, M, W, torch):
+    """4096 independent integrals run to completion together; one step = one
+    whole batch (every integral's itmax iterations, one persistent launch per
+    iteration)."""
+    probs = W.config_batch(n=args.batch_size, precision=args.precision)
+    ws = torch.empty(M.batch_workspace_bytes(probs), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        M.batch_integrate(probs, ws=ws)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(M.batch_integrate(probs, ws=ws)[1])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    calls = sum(s.calls for s in stats)
+    sample_s = sum(s.sample_ms for s in stats) / 1e3
+    ops = 0.0
+    for p in probs:
+        gmp = M.shape(p["dim"], p["maxcalls"])
+        per = ops_per_sample(p, gmp, adjust=True)
+        if p["precision"] == "fp32":
+            per -= (math.ceil(p["dim"] / 2) - math.ceil(p["dim"] / 4)) * 51
+        ops += per * gmp[1] * gmp[2] * p["itmax"]
+    ops *= args.steps
+    line = _base_line(args, "batch_4096_mixed", calls / el, el / args.steps * 1e3,
+                      "f64" if args.precision == "fp64" else "f32-eval/f64-accumulate",
+                      {"integrals": len(probs), "dim": "U{2..10}", "maxcalls": "log-U[1e4,1e7]",
+                       "nbins": "U{100..500}", "itmax": probs[0]["itmax"],
+                       "integrands": "Gaussian product / corner peak",
+                       "step": "one whole batch to completion (mc_batch_integrate)"})
+    line["roofline"] = {"bound": "alu", "achieved": ops / sample_s / 1e12,
+                        "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                        "frac": ops / sample_s / VALU_PEAK_OPS, "traffic": None,
+                        "kernel": "vsample_batch_kernel",
+                        "avg_launch_ms": sample_s / sum(s.steps for s in stats) * 1e3}
+    line["kernel_samples_per_s"] = calls / sample_s
+    line["steps_per_batch"] = stats[0].steps
+    print(json.dumps(line))
+
+
+def bench_serve(args, M, W, torch):
+    """A Poisson stream of requests served with continuous batching; reports
+    samples/s over the run and p50/p99 time from arrival to answer."""
+    arrivals, probs = W.served_requests(n=args.requests, rate=args.rate, precision=args.precision)
+    srv = M.Server(ws_bytes=args.serve_gib * 2**30, arena_bytes=args.serve_gib * 2**30 // 2,
+                   max_active=8192)
+    # warm-up: a few requests through the server before the clock starts
+    for p in probs[:8]:
+        srv.submit(dict(p, seed=p["seed"] + 10**6))
+    while True:
+        a, q, _ = srv.step()
+        for rid in srv.finished():
+            srv.release(rid)
+        if a == 0 and q == 0:
+            break
+    torch.cuda.synchronize()
+    done_at, ids = {}, {}
+    nxt, n = 0, len(probs)
+    t0 = time.perf_counter()
+    while len(done_at) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            ids[srv.submit(probs[nxt])] = nxt
+            nxt += 1
+        if len(ids) > len(done_at):
+            srv.step()
+            t = time.perf_counter() - t0
+            for rid in srv.finished():
+                done_at[ids[rid]] = t
+        elif nxt < n:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    lat = np.array([done_at[i] - arrivals[i] for i in range(n)]) * 1e3
+    fails = 0
+    for rid in list(ids):
+        state, _, _ = srv.poll(rid)
+        fails += state != M.REQ_DONE
+    srv.close()
+    line = _base_line(args, "served_poisson", st.calls / el, el * 1e3,
+                      "f64" if args.precision == "fp64" else "f32-eval/f64-accumulate",
+                      {"requests": n, "rate_per_s": args.rate, "dim": "U{3..10}",
+                       "tau_rel": "log-U[1e-5,1e-2]", "maxcalls": "1e5/1e6/1e7 by target",
+                       "nbins": 100, "step": "the whole served stream"})
+    line["steps"] = 1
+    line["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "mean": float(lat.mean()), "max": float(lat.max())}
+    line["served"] = {"failed": fails, "server_steps": st.steps, "max_active": st.max_active,
+                      "sampling_ms": st.sample_ms, "wall_ms": el * 1e3}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +215,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="evaluation precision for the batch and serve workloads")
+    ap.add_argument("--batch-size", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--serve-gib", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -135,6 +246,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args, M, W, torch)
+    if args.workload == "serve":
+        return bench_serve(args, M, W, torch)
     name, make = WORKLOADS[args.workload]
     prob = make(W, 1)
     bp = M.BoundProblem(prob, args.blocks, args.threads)

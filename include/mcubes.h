@@ -234,6 +234,9 @@ mc_status mc_server_step(mc_server *srv, int32_t *active, int32_t *queued, int32
  * status (may be NULL) holds its final status. */
 mc_status mc_server_poll(mc_server *srv, int64_t id, int32_t *state, mc_result *out,
                          mc_status *status);
+/* Ids of the requests that finished (done or failed) in the last step, up to
+ * cap of them; *n is how many were written. */
+mc_status mc_server_finished(mc_server *srv, int64_t *ids, int32_t cap, int32_t *n);
 /* Forgets a finished request. */
 mc_status mc_server_release(mc_server *srv, int64_t id);
 mc_status mc_server_stats(mc_server *srv, mc_batch_stats *stats);

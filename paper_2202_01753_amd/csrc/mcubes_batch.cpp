@@ -192,6 +192,7 @@ struct mc_server {
     std::unordered_map<int64_t, std::unique_ptr<Request>> all;
     std::deque<Request *> queue;
     std::vector<Request *> active;
+    std::vector<int64_t> last_finished;  // ids finished in the last step
     StepNeed need;  // of the active set
     std::vector<char> staging;
     std::vector<double> res;
@@ -242,6 +243,7 @@ struct mc_server {
     }
 
     void finish(Request *r, int32_t state, mc_status status) {
+        last_finished.push_back(r->id);
         r->state = state;
         r->status = status;
         arena->release(r->block_off, r->block_bytes);
@@ -350,6 +352,7 @@ struct mc_server {
 
     mc_status step(int32_t *n_finished) {
         *n_finished = 0;
+        last_finished.clear();
         mc_status st = admit();
         if (st != MC_OK) return st;
         if (active.empty()) return MC_OK;
@@ -529,6 +532,14 @@ mc_status mc_server_poll(mc_server *srv, int64_t id, int32_t *state, mc_result *
     *state = r.state;
     if (status) *status = r.status;
     if (out && r.state == MC_REQ_DONE) *out = r.result;
+    return MC_OK;
+}
+
+mc_status mc_server_finished(mc_server *srv, int64_t *ids, int32_t cap, int32_t *n) {
+    if (!srv || !n || (cap > 0 && !ids)) return MC_EINVAL;
+    const int32_t k = std::min<int32_t>(cap, (int32_t)srv->last_finished.size());
+    for (int32_t i = 0; i < k; ++i) ids[i] = srv->last_finished[i];
+    *n = k;
     return MC_OK;
 }
 

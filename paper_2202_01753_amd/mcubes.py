@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_init_grid", "mc_weighted_estimate",
            "mc_integrate", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
-           "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_release",
+           "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
+           "mc_server_release",
            "mc_server_stats", "mc_server_destroy")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
@@ -108,6 +109,8 @@ def lib() -> C.CDLL:
             "mc_server_step": ([vp] + [C.POINTER(C.c_int32)] * 3, C.c_int32),
             "mc_server_poll": ([vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(Result),
                                 C.POINTER(C.c_int32)], C.c_int32),
+            "mc_server_finished": ([vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)],
+                                   C.c_int32),
             "mc_server_release": ([vp, C.c_int64], C.c_int32),
             "mc_server_stats": ([vp, C.POINTER(BatchStats)], C.c_int32),
             "mc_server_destroy": ([vp], C.c_int32),
@@ -380,6 +383,13 @@ class Server:
             res = {"estimate": r.estimate, "error": r.error, "chi2_dof": r.chi2_dof,
                    "iterations": r.iterations, "converged": bool(r.converged), "calls": r.calls}
         return st.value, res, status.value
+
+    def finished(self, cap: int = 65536):
+        """Ids of the requests that finished in the last step."""
+        ids = (C.c_int64 * cap)()
+        n = C.c_int32()
+        _check(lib().mc_server_finished(self.h, ids, cap, C.byref(n)), "mc_server_finished")
+        return list(ids[:n.value])
 
     def release(self, rid: int):
         _check(lib().mc_server_release(self.h, rid), "mc_server_release")

@@ -122,3 +122,48 @@ def config_gauss8(seed=1, rng_seed=88, maxcalls=1_000_000_000, itmax=20, **kw):
     w = np.full(8, 0.01)
     return _problem("gauss_product", np.concatenate([c, w]), 8, maxcalls, 500, itmax, alpha=1.5,
                     seed=seed, **kw)
+
+
+def config_batch(n=4096, seed=4096, itmax=10, precision="fp64"):
+    """n independent integrals: d ~ U{2..10}; Gaussian product (c ~ U(0.3,0.7),
+    w ~ U(0.05,0.2)) or corner peak (a ~ U(0.5,2)) with probability 1/2 each;
+    samples per iteration log-uniform on [1e4, 1e7]; nb ~ U{100..500}; each
+    with its own parameter and sampling seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        d = int(rng.integers(2, 11))
+        N = int(10 ** rng.uniform(4.0, 7.0))
+        nb = int(rng.integers(100, 501))
+        sub = int(rng.integers(0, 2**31))
+        kw = dict(maxcalls=N, nbins=nb, itmax=itmax, alpha=1.5, seed=1 + i, precision=precision)
+        if rng.random() < 0.5:
+            out.append(gauss_product(d, sub, (0.3, 0.7), (0.05, 0.2), **kw))
+        else:
+            out.append(corner_peak(d, sub, (0.5, 2.0), **kw))
+    return out
+
+
+def served_requests(n=2000, rate=2000.0, seed=2000, precision="fp64", itmax=50):
+    """A seeded Poisson stream of integration requests (mean `rate` per
+    second): arrival times (s) and problems.  d ~ U{3..10}; target relative
+    error log-uniform on [1e-5, 1e-2]; Gaussian product (the small
+    configuration's ranges) or, for d >= 4 with probability 1/2, Gaussian
+    peaks times two tables (the table configuration's ranges); samples per
+    iteration 1e5 for targets >= 1e-3, 1e6 down to 1e-4, 1e7 below; 100
+    bins; at most `itmax` iterations."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    out = []
+    for i in range(n):
+        d = int(rng.integers(3, 11))
+        tau = float(10 ** rng.uniform(-5.0, -2.0))
+        N = 100_000 if tau >= 1e-3 else (1_000_000 if tau >= 1e-4 else 10_000_000)
+        sub = int(rng.integers(0, 2**31))
+        kw = dict(maxcalls=N, nbins=100, itmax=itmax, alpha=1.5, seed=1 + i, tau_rel=tau,
+                  precision=precision)
+        if d >= 4 and rng.random() < 0.5:
+            out.append(gauss_tables(d, sub, (0.2, 0.8), (0.02, 0.1), **kw))
+        else:
+            out.append(gauss_product(d, sub, (0.3, 0.7), (0.05, 0.2), **kw))
+    return arrivals, out
