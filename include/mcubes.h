@@ -85,6 +85,9 @@ typedef struct mc_problem {
     uint64_t seed;           /* random-number key */
     int32_t blocks;          /* workgroups of the sampling kernel; 0 = fill the device */
     int32_t threads;         /* threads per workgroup, a multiple of 64 in 64..1024; 0 = 512 */
+    int32_t one_d;           /* 1: the m-Cubes1D variant (Sec. V): bin contributions of the first
+                                axis only, and its adjusted boundaries shared by every axis; meant
+                                for fully symmetric integrands.  0: separate grids per axis */
 } mc_problem;
 
 typedef struct mc_result {
@@ -150,6 +153,12 @@ mc_status mc_sample_iteration(const mc_problem *prob, uint32_t iter, int32_t adj
  * left unchanged.  Host only; h_grid is updated in place. */
 mc_status mc_refine_grid(int32_t dim, int32_t nbins, double alpha, const double *h_hist,
                          double *h_grid);
+
+/* The m-Cubes1D adjustment (Sec. V): the first axis's boundaries adjusted
+ * from the first axis's contributions (h_hist row 0), then copied to every
+ * axis.  Host only; h_grid is updated in place. */
+mc_status mc_refine_grid_1d(int32_t dim, int32_t nbins, double alpha, const double *h_hist,
+                            double *h_grid);
 
 /* Init-Bins (Alg. 2): nbins equal bins per axis.  Host only. */
 mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid);

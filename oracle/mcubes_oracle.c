@@ -43,6 +43,10 @@
  *     from the same words, the map and the integrand in single precision
  *     (constants, each bin's left boundary and width, and the tables rounded
  *     to float from FP64), then I_k and everything after it in FP64 as above.
+ *   - m-Cubes1D variant (Sec. V, "The m-Cubes1D variant"): the bin
+ *     contributions are collected for the first axis only, its boundaries are
+ *     adjusted from them, and every axis takes those boundaries, so all axes
+ *     share one grid (meant for fully symmetric integrands).
  *
  * Build with -ffp-contract=off: every rounding below is the one written.
  */
@@ -74,6 +78,7 @@ typedef struct {
     double alpha, tau_rel;
     uint64_t seed;
     int32_t precision;      /* 0: FP64, 1: FP32 evaluation with FP64 accumulation */
+    int32_t one_d;          /* 1: the m-Cubes1D variant */
 } orc_problem;
 
 /* ------------------------------------------------------------------ */
@@ -319,6 +324,7 @@ static int validate(const orc_problem *P)
     if (P->itmax < 1 || P->ita < 0 || P->ita > P->itmax) return ORC_EINVAL;
     if (!(P->alpha > 0.0) || !(P->tau_rel >= 0.0)) return ORC_EINVAL;
     if (P->precision != 0 && P->precision != 1) return ORC_EINVAL;
+    if (P->one_d != 0 && P->one_d != 1) return ORC_EINVAL;
     if (params_expected(P->integrand, d) < 0) return ORC_EINVAL;
     if (P->integrand == ORC_F_GAUSS_TABLES && (d < 4 || P->tables == NULL)) return ORC_EINVAL;
     for (int j = 0; j < d; ++j)
@@ -524,7 +530,8 @@ int orc_vsample(const orc_problem *P, uint32_t iter, const double *grid, int64_t
             }
             if (bins) {
                 double sq = Ik * Ik;
-                for (int j = 0; j < d; ++j) nsum_add(&bins[(size_t)j * nb + bin[j]], sq);
+                int axes = P->one_d ? 1 : d;
+                for (int j = 0; j < axes; ++j) nsum_add(&bins[(size_t)j * nb + bin[j]], sq);
             }
             if (strace) {
                 double *r = strace + ((t - t0) * p + k) * rec;
@@ -622,6 +629,14 @@ void orc_refine(int32_t d, int32_t nb, double alpha, const double *hist, double 
     free(old);
 }
 
+/* m-Cubes1D bin adjustment: the first axis's boundaries adjusted from its
+ * contributions, then copied to every axis. */
+void orc_refine_1d(int32_t d, int32_t nb, double alpha, const double *hist, double *grid)
+{
+    orc_refine(1, nb, alpha, hist, grid);
+    for (int j = 1; j < d; ++j) memcpy(grid + (size_t)j * (nb + 1), grid, sizeof(double) * (nb + 1));
+}
+
 /* Weighted-Estimates: inverse-variance weighted mean of the k iteration
  * estimates, its standard deviation and chi^2 per degree of freedom.       */
 void orc_weighted(int32_t k, const double *I, const double *var, double *Ibar, double *sigma,
@@ -683,7 +698,12 @@ int orc_integrate(const orc_problem *P, double *res, int64_t *ires, double *it_I
         if (rc != ORC_OK) break;
         k = it + 1;
         orc_weighted(k, Is, Vs, &Ibar, &sigma, &chi2);
-        if (adjust) orc_refine(d, nb, P->alpha, hist, grid);
+        if (adjust) {
+            if (P->one_d)
+                orc_refine_1d(d, nb, P->alpha, hist, grid);
+            else
+                orc_refine(d, nb, P->alpha, hist, grid);
+        }
         if (k >= 2 && P->tau_rel > 0.0 && sigma <= P->tau_rel * fabs(Ibar)) {
             converged = 1;
             break;

@@ -8,7 +8,8 @@ A problem is a plain dict with the keys ``integrand`` (one of "const",
 "gauss_product", "corner_peak", "gauss_tables"), ``params``, ``tables``
 (or None), ``dim``, ``lo``, ``hi``, ``maxcalls``, ``nbins``, ``itmax``,
 ``ita``, ``alpha``, ``tau_rel``, ``seed`` and optionally ``precision``
-("fp64", the default, or "fp32" for FP32 evaluation with FP64 accumulation).
+("fp64", the default, or "fp32" for FP32 evaluation with FP64 accumulation)
+and ``one_d`` (True for the m-Cubes1D variant).
 """
 from __future__ import annotations
 
@@ -48,6 +49,7 @@ class _Problem(C.Structure):
         ("tau_rel", C.c_double),
         ("seed", C.c_uint64),
         ("precision", C.c_int32),
+        ("one_d", C.c_int32),
     ]
 
 
@@ -95,6 +97,8 @@ def lib():
         L.orc_init_grid.restype = None
         L.orc_refine.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp]
         L.orc_refine.restype = None
+        L.orc_refine_1d.argtypes = [C.c_int32, C.c_int32, C.c_double, dp, dp]
+        L.orc_refine_1d.restype = None
         L.orc_weighted.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
         L.orc_weighted.restype = None
         L.orc_integrate.argtypes = [C.POINTER(_Problem), dp, C.POINTER(C.c_int64), dp, dp, dp]
@@ -124,7 +128,8 @@ class _Bound:
             _dp(self.lo), _dp(self.hi), int(prob["maxcalls"]), int(prob["nbins"]),
             int(prob["itmax"]), int(prob.get("ita", prob["itmax"])), float(prob["alpha"]),
             float(prob.get("tau_rel", 0.0)), int(prob["seed"]) & (2**64 - 1),
-            1 if prob.get("precision", "fp64") == "fp32" else 0)
+            1 if prob.get("precision", "fp64") == "fp32" else 0,
+            1 if prob.get("one_d", False) else 0)
 
 
 def philox4x32_10(ctr, key):
@@ -211,6 +216,14 @@ def refine(d: int, nb: int, alpha: float, hist, grid):
     out = _f64(grid).copy()
     h = _f64(hist)
     lib().orc_refine(d, nb, alpha, _dp(h), _dp(out))
+    return out
+
+
+def refine_1d(d: int, nb: int, alpha: float, hist, grid):
+    """m-Cubes1D adjustment: axis 0 from its contributions, copied to every axis."""
+    out = _f64(grid).copy()
+    h = _f64(hist)
+    lib().orc_refine_1d(d, nb, alpha, _dp(h), _dp(out))
     return out
 
 

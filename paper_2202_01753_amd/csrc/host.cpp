@@ -82,6 +82,7 @@ mc_status validate(const mc_problem *pr) {
     if (lattice(d, pr->maxcalls, &g, &m, &p) != MC_OK) return MC_EINVAL;
     if (g > kMaxIntervals) return MC_EINVAL;
     if (pr->precision != MC_FP64 && pr->precision != MC_FP32_EVAL) return MC_EINVAL;
+    if (pr->one_d != 0 && pr->one_d != 1) return MC_EINVAL;
     if (is_fp32(pr) && g > (int64_t(1) << 24)) return MC_EINVAL;  // digits exact in float
     if (pr->nbins < 2 || pr->nbins > (1 << 20)) return MC_EINVAL;
     if (lds_bytes_of(d, pr->nbins, true, is_fp32(pr)) > kLdsLimit) return MC_EINVAL;
@@ -185,6 +186,12 @@ void refine(int d, int nb, double alpha, const double *hist, double *grid) {
     });
 }
 
+void refine_1d(int d, int nb, double alpha, const double *hist, double *grid) {
+    std::vector<double> sm(nb), r(nb), prev(nb + 1);
+    refine_axis(nb, alpha, hist, grid, sm, r, prev);
+    for (int j = 1; j < d; ++j) std::copy(grid, grid + nb + 1, grid + (size_t)j * (nb + 1));
+}
+
 void weighted(int k, const double *I, const double *var, double *out) {
     int zeros = 0;
     double zsum = 0.0;
@@ -233,6 +240,7 @@ void sample_args(const mc_problem *pr, int64_t g, int64_t m, int64_t p, uint32_t
     a->g = (int32_t)g;
     a->hist = adjust ? 1 : 0;
     a->kind = pr->integrand * 32 + pr->dim;
+    a->one_d = pr->one_d ? 1 : 0;
     a->s = (double)nb / (double)g;
     a->s32 = (float)a->s;
     a->inv = 1.0 / (double)(m * p);

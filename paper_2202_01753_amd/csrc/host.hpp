@@ -57,6 +57,8 @@ void refine_axis(int nb, double alpha, const double *C, double *B, std::vector<d
                  std::vector<double> &r, std::vector<double> &prev);
 // Adjust-Bin-Bounds of all axes, the axes on the host pool.
 void refine(int d, int nb, double alpha, const double *hist, double *grid);
+// m-Cubes1D adjustment: axis 0 from hist row 0, then copied to every axis.
+void refine_1d(int d, int nb, double alpha, const double *hist, double *grid);
 // Weighted-Estimates over k iterations: out = [mean, sigma, chi2/dof].
 void weighted(int k, const double *I, const double *var, double *out);
 

@@ -152,7 +152,7 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     HIP_TRY(launch_finalize(a.partials, blocks, d * nb, G.hist_stride, adjust ? 1 : 0, a.flag,
                             out_dev, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[2], stream));
-    if (adjust && d > 1) AxisPool::get().prime(spin_us);
+    if (adjust && d > 1 && !pr->one_d) AxisPool::get().prime(spin_us);
     const size_t nout = 4 + (adjust ? (size_t)d * nb : 0);
     HIP_TRY(hipMemcpyAsync(out_host, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -271,6 +271,14 @@ mc_status mc_refine_grid(int32_t dim, int32_t nbins, double alpha, const double 
     return MC_OK;
 }
 
+mc_status mc_refine_grid_1d(int32_t dim, int32_t nbins, double alpha, const double *h_hist,
+                            double *h_grid) {
+    if (dim < 1 || dim > MC_MAX_DIM || nbins < 2 || !(alpha > 0.0) || !h_hist || !h_grid)
+        return MC_EINVAL;
+    refine_1d(dim, nbins, alpha, h_hist, h_grid);
+    return MC_OK;
+}
+
 mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid) {
     if (dim < 1 || dim > MC_MAX_DIM || nbins < 2 || !h_grid) return MC_EINVAL;
     init_grid(dim, nbins, h_grid);
@@ -317,7 +325,12 @@ mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void
         Vs[it] = buf[1];
         k = it + 1;
         weighted(k, Is.data(), Vs.data(), est);
-        if (adjust) refine(d, nb, prob->alpha, buf.data() + 4, grid.data());
+        if (adjust) {
+            if (prob->one_d)
+                refine_1d(d, nb, prob->alpha, buf.data() + 4, grid.data());
+            else
+                refine(d, nb, prob->alpha, buf.data() + 4, grid.data());
+        }
         if (k >= 2 && prob->tau_rel > 0.0 && est[1] <= prob->tau_rel * std::fabs(est[0])) {
             converged = 1;
             break;

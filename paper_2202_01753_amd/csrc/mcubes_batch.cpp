@@ -385,7 +385,8 @@ struct mc_server {
             b.refine = adjust ? 1 : 0;
             next_grid[i] = reinterpret_cast<double *>(ws + r->off_grid[1 - r->cur]);
             if (adjust) {
-                for (int j = 0; j < r->prob.dim; ++j) {
+                const int axes = r->prob.one_d ? 1 : r->prob.dim;  // m-Cubes1D: axis 0, then copied
+                for (int j = 0; j < axes; ++j) {
                     axis_item[2 * n_axes] = i;
                     axis_item[2 * n_axes + 1] = j;
                     ++n_axes;

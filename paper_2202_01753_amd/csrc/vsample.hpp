@@ -314,8 +314,10 @@ __device__ __forceinline__ void cube_pass(const SampleArgs &a, const LdsView<F32
         }
         if (a.hist) {
             const double sq = Ik * Ik;
+            const int axes = a.one_d ? 1 : D;
 #pragma unroll
-            for (int j = 0; j < D; ++j) atomicAdd(&sH[j * nb + bin[j]], sq);
+            for (int j = 0; j < D; ++j)
+                if (j < axes) atomicAdd(&sH[j * nb + bin[j]], sq);
         }
         if (traced) {
             double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;

@@ -117,7 +117,8 @@ __global__ void __launch_bounds__(kFinThreads) batch_finalize_kernel(const Batch
 // across the block, the running sums and the equal-share rebinning in order
 // by one lane (the same steps and summation order as the host version; pow
 // and log are the device library's).  Reads the axis's histogram from out
-// and its boundaries from a.grid, writes the new boundaries to next.
+// and its boundaries from a.grid, writes the new boundaries to next; for the
+// m-Cubes1D variant (only axis 0 listed) to every axis.
 constexpr int kRefThreads = 64;
 
 __global__ void __launch_bounds__(kRefThreads)
@@ -148,8 +149,10 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
         usable = (S > 0.0) && isfinite(S);
     }
     __syncthreads();
+    const int copies = it.a.one_d ? (it.a.kind & 31) : 1;
     if (!usable) {  // no usable weight: the axis keeps its boundaries
-        for (int i = threadIdx.x; i <= nb; i += kRefThreads) Bn[i] = B[i];
+        for (int c = 0; c < copies; ++c)
+            for (int i = threadIdx.x; i <= nb; i += kRefThreads) Bn[(size_t)c * (nb + 1) + i] = B[i];
         return;
     }
     const double S = total_s;
@@ -162,7 +165,8 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
     double R = 0.0;
     for (int i = 0; i < nb; ++i) R = R + r[i];
     if (!(R > 0.0)) {
-        for (int i = 0; i <= nb; ++i) Bn[i] = B[i];
+        for (int c = 0; c < copies; ++c)
+            for (int i = 0; i <= nb; ++i) Bn[(size_t)c * (nb + 1) + i] = B[i];
         return;
     }
     const double per_bin = R / (double)nb;
@@ -182,6 +186,8 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
         Bn[k] = prev_edge;
     }
     Bn[nb] = 1.0;
+    for (int c = 1; c < copies; ++c)
+        for (int i = 0; i <= nb; ++i) Bn[(size_t)c * (nb + 1) + i] = Bn[i];
 }
 
 }  // namespace

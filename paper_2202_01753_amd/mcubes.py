@@ -22,7 +22,8 @@ OK, EINVAL, EWORKSPACE, ENONFINITE, EDEVICE = 0, 1, 2, 3, 4
 INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
-           "mc_sample_iteration", "mc_refine_grid", "mc_init_grid", "mc_weighted_estimate",
+           "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
+           "mc_weighted_estimate",
            "mc_integrate", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
            "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
            "mc_server_release",
@@ -56,6 +57,7 @@ class Problem(C.Structure):
         ("seed", C.c_uint64),
         ("blocks", C.c_int32),
         ("threads", C.c_int32),
+        ("one_d", C.c_int32),
     ]
 
 
@@ -97,6 +99,7 @@ def lib() -> C.CDLL:
             "mc_sample_iteration": ([P, C.c_uint32, C.c_int32, dp, vp, sz, vp, dp, dp, vp, sz,
                                      C.c_int64, C.c_int64], C.c_int32),
             "mc_refine_grid": ([C.c_int32, C.c_int32, C.c_double, dp, dp], C.c_int32),
+            "mc_refine_grid_1d": ([C.c_int32, C.c_int32, C.c_double, dp, dp], C.c_int32),
             "mc_init_grid": ([C.c_int32, C.c_int32, dp], C.c_int32),
             "mc_weighted_estimate": ([C.c_int32, dp, dp, dp], C.c_int32),
             "mc_integrate": ([P, vp, sz, vp, C.POINTER(Result), dp, dp, C.POINTER(Timing)],
@@ -157,7 +160,8 @@ class BoundProblem:
             itmax=int(prob["itmax"]), ita=int(prob.get("ita", prob["itmax"])),
             precision=PRECISIONS[prob.get("precision", "fp64")],
             alpha=float(prob["alpha"]), tau_rel=float(prob.get("tau_rel", 0.0)),
-            seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads))
+            seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads),
+            one_d=1 if prob.get("one_d", False) else 0)
 
     @property
     def ref(self):
@@ -180,6 +184,13 @@ def refine_grid(dim: int, nbins: int, alpha: float, hist, grid):
     out = _f64(grid).copy()
     h = _f64(hist)
     _check(lib().mc_refine_grid(dim, nbins, alpha, _dp(h), _dp(out)), "mc_refine_grid")
+    return out
+
+
+def refine_grid_1d(dim: int, nbins: int, alpha: float, hist, grid):
+    out = _f64(grid).copy()
+    h = _f64(hist)
+    _check(lib().mc_refine_grid_1d(dim, nbins, alpha, _dp(h), _dp(out)), "mc_refine_grid_1d")
     return out
 
 

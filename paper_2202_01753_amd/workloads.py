@@ -9,7 +9,8 @@ A problem is a plain dict with the keys ``integrand`` ("const",
 ``tables`` (float64 of 2*256*256, or None), ``dim``, ``lo``, ``hi``,
 ``maxcalls``, ``nbins``, ``itmax``, ``ita``, ``alpha``, ``tau_rel``,
 ``seed`` (the sampling seed, separate from the parameter seed) and
-``precision`` ("fp64", or "fp32" for FP32 evaluation with FP64 accumulation).
+``precision`` ("fp64", or "fp32" for FP32 evaluation with FP64 accumulation)
+and ``one_d`` (True: the m-Cubes1D variant, one grid shared by all axes).
 
 Parameter layouts:
   const          [v]
@@ -25,7 +26,7 @@ TABLE_N = 256
 
 
 def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=None, hi=None,
-             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64"):
+             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64", one_d=False):
     return {
         "integrand": integrand,
         "params": np.ascontiguousarray(params, dtype=np.float64),
@@ -41,6 +42,7 @@ def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=
         "tau_rel": float(tau_rel),
         "seed": int(seed),
         "precision": precision,
+        "one_d": bool(one_d),
     }
 
 
@@ -93,6 +95,17 @@ def gauss_tables(dim, rng_seed, c_range=(0.2, 0.8), w_range=(0.02, 0.1), maxcall
     tables = smooth_tables(rng)
     return _problem("gauss_tables", np.concatenate([c, w]), dim, maxcalls, nbins, itmax,
                     tables=tables, **kw)
+
+
+def symmetric_gauss(dim, c=0.5, w=0.1, maxcalls=10_000, nbins=100, itmax=10, **kw):
+    """A fully symmetric Gaussian product: the same centre and width on every axis."""
+    return _problem("gauss_product", np.concatenate([np.full(dim, c), np.full(dim, w)]), dim,
+                    maxcalls, nbins, itmax, **kw)
+
+
+def symmetric_corner(dim, a=1.0, maxcalls=10_000, nbins=100, itmax=10, **kw):
+    """A fully symmetric corner peak: the same coefficient on every axis."""
+    return _problem("corner_peak", np.full(dim, a), dim, maxcalls, nbins, itmax, **kw)
 
 
 # ---- the benchmark configurations ------------------------------------------------------------

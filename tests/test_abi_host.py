@@ -139,3 +139,16 @@ def test_null_arguments_rejected():
     assert L.mc_integrate(None, None, 0, None, None, None, None, None) == M.EINVAL
     assert L.mc_refine_grid(2, 10, 1.5, None, None) == M.EINVAL
     assert L.mc_weighted_estimate(0, None, None, None) == M.EINVAL
+
+
+def test_refine_1d_matches_oracle_bit_for_bit():
+    rng = np.random.default_rng(11)
+    for d, nb in [(2, 50), (6, 500), (10, 100)]:
+        hist = rng.gamma(0.4, size=d * nb) ** 2
+        grid = O.init_grid(d, nb)
+        for _ in range(3):
+            a = M.refine_grid_1d(d, nb, 1.5, hist, grid)
+            assert np.array_equal(a, O.refine_1d(d, nb, 1.5, hist, grid))
+            grid = a
+        rows = grid.reshape(d, nb + 1)
+        assert all(np.array_equal(rows[0], rows[j]) for j in range(d))

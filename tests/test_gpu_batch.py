@@ -139,3 +139,14 @@ def test_server_admits_by_memory_and_matches_alone():
     s = srv.stats()
     assert 0 < s.steps <= steps and s.calls > 0
     srv.close()
+
+
+def test_batch_one_d_matches_single_path():
+    probs = [W.symmetric_gauss(5, c=0.45, w=0.12, maxcalls=200_000, nbins=60, itmax=6, seed=3, one_d=True),
+             W.symmetric_corner(4, a=1.3, maxcalls=100_000, nbins=60, itmax=5, seed=4, one_d=True),
+             W.config_small(seed=2)]
+    mixed, _ = M.batch_integrate(probs)
+    for i, p in enumerate(probs):
+        single = M.integrate(p)
+        _close(mixed[i], {"estimate": single.estimate, "error": single.error,
+                          "iterations": single.iterations, "converged": single.converged})

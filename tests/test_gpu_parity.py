@@ -120,7 +120,12 @@ def _lockstep(prob, iters=None, threads=0, blocks=0):
         ref = O.vsample(prob, it, grid, hist=adjust, trace=True)
         scale = _compare_records(prob, gpu, ref, f"iter {it}")
         _compare_totals(gpu, ref, scale, f"iter {it}", _tol(prob))
-        if adjust:
+        if adjust and prob.get("one_d"):
+            a = M.refine_grid_1d(d, nb, prob["alpha"], gpu["hist"], grid)
+            b = O.refine_1d(d, nb, prob["alpha"], gpu["hist"], grid)
+            assert np.array_equal(a, b), f"iter {it}: refined grids differ"
+            grid = a
+        elif adjust:
             a = M.refine_grid(d, nb, prob["alpha"], gpu["hist"], grid)
             b = O.refine(d, nb, prob["alpha"], gpu["hist"], grid)
             assert np.array_equal(a, b), f"iter {it}: refined grids differ"
@@ -330,4 +335,27 @@ def test_fp32_integrate_accuracy():
     prob = W.corner_peak(5, 14, maxcalls=200_000, nbins=100, itmax=12, tau_rel=1e-3, seed=5)
     g = M.integrate(_as_fp32(prob))
     assert g.converged and g.error <= 1e-3 * abs(g.estimate)
+    assert abs(g.estimate - CF.exact(prob)) < 5 * g.error
+
+
+# ---------------------------------------------------------------- m-Cubes1D
+
+@pytest.mark.parametrize("make", [
+    lambda: W.symmetric_gauss(4, c=0.45, w=0.12, maxcalls=20_000, nbins=50, itmax=3, seed=6, one_d=True),
+    lambda: W.symmetric_corner(3, a=1.2, maxcalls=8_000, nbins=40, itmax=3, seed=7, one_d=True),
+    lambda: W.symmetric_corner(5, a=0.9, maxcalls=30_000, nbins=40, itmax=2, seed=8, one_d=True,
+                               precision="fp32"),
+], ids=["gauss4", "corner3", "corner5-fp32"])
+def test_one_d_lockstep(make):
+    grid = _lockstep(make())
+    rows = grid.reshape(make()["dim"], -1)
+    assert all(np.array_equal(rows[0], rows[j]) for j in range(len(rows)))
+
+
+def test_one_d_integrate_matches_oracle():
+    prob = W.symmetric_gauss(5, c=0.45, w=0.12, maxcalls=200_000, nbins=60, itmax=6, seed=3, one_d=True)
+    g = M.integrate(prob)
+    o = O.integrate(prob)
+    assert g.estimate == pytest.approx(o["estimate"], rel=1e-11)
+    assert np.array_equal(g.grid.reshape(5, -1)[0], g.grid.reshape(5, -1)[4])
     assert abs(g.estimate - CF.exact(prob)) < 5 * g.error

@@ -509,3 +509,45 @@ def test_fp32_estimator_unbiased():
         Is[s], Vs[s] = r["I"], r["var"]
     assert abs(Is.mean() - exact) < 4 * Is.std(ddof=1) / math.sqrt(n)
     assert abs(Vs.mean() / Is.var(ddof=1) - 1.0) < 0.25
+
+
+# ---------------------------------------------------------------- m-Cubes1D variant
+
+def test_one_d_histogram_is_the_first_axis_row():
+    """The 1D variant collects exactly the first axis's contributions of the
+    full algorithm (same samples), and nothing for the other axes."""
+    prob = W.symmetric_gauss(4, maxcalls=20_000, nbins=40, itmax=3, seed=5)
+    grid = O.init_grid(4, 40)
+    full = O.vsample(prob, 1, grid)
+    one = O.vsample(dict(prob, one_d=True), 1, grid)
+    assert np.array_equal(one["hist"][:40], full["hist"][:40])
+    assert not one["hist"][40:].any()
+    assert (one["I"], one["var"]) == (full["I"], full["var"])
+
+
+def test_one_d_refinement_shares_the_first_axis():
+    rng = np.random.default_rng(3)
+    d, nb = 5, 30
+    hist = rng.gamma(0.5, size=d * nb)
+    grid = O.init_grid(d, nb)
+    out = O.refine_1d(d, nb, 1.5, hist, grid).reshape(d, nb + 1)
+    ref = O.refine(1, nb, 1.5, hist[:nb], grid[:nb + 1])
+    for j in range(d):
+        assert np.array_equal(out[j], ref)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.symmetric_gauss(5, c=0.45, w=0.12, maxcalls=200_000, nbins=60, itmax=8, seed=3),
+    lambda: W.symmetric_corner(4, a=1.3, maxcalls=100_000, nbins=60, itmax=8, seed=4),
+])
+def test_one_d_on_symmetric_integrands(make):
+    """On a fully symmetric integrand the shared grid adapts as well as d
+    separate ones: both runs are accurate and agree statistically."""
+    prob = make()
+    full, one = O.integrate(prob), O.integrate(dict(prob, one_d=True))
+    exact = CF.exact(prob)
+    for r in (full, one):
+        assert abs(r["estimate"] - exact) < 4.5 * r["error"]
+    g = one["grid"].reshape(prob["dim"], -1)
+    assert all(np.array_equal(g[0], g[j]) for j in range(prob["dim"]))
+    assert one["error"] < 2.0 * full["error"]
