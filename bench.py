@@ -3,11 +3,13 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--workload tables|corner8|gauss8|small|batch|serve] [--precision fp64|fp32]
 
-One step is one complete m-Cubes run (mc_integrate: every iteration of
-sampling kernel + fixed-order reduction + read-back + host weighting, bin
-adjustment and convergence check) on the workload's synthetic inputs; the
-device workspace is allocated before the timed region.  `value` is integrand
-samples per second over the K timed steps (iterations * m * p per step).
+One step is one complete m-Cubes run (mc_integrate_prepared: every
+iteration of sampling kernel + fixed-order reduction + read-back + host
+weighting, bin adjustment and convergence check) on the workload's synthetic
+inputs; the workspace is allocated and the integrand's constants and tables
+are uploaded (mc_prepare) before the timed region, so the inputs are resident
+in device memory when it starts.  `value` is integrand samples per second
+over the K timed steps (iterations * m * p per step).
 
 The roofline entry is for the sampling kernel: its average launch duration
 comes from HIP events recorded by the library on the launch stream, and its
@@ -19,9 +21,11 @@ one host core over a bounded block of sub-cubes of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -36,15 +40,18 @@ CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
 VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 lane-ops/s
 
 
-def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
+PHILOX_BLOCK_OPS = 17 + 18
+
+
+def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float:
     """Algorithmic VALU lane-operations per sample of the FP64 path.
 
     Counted from the method's steps at one issue slot per full-rate VALU
     instruction (measured on gfx950: 32x32->64 integer products, FP64 add/mul/
-    fma and conversions all issue at the full rate; v_rcp_f64 counts 4), with
-    work that is uniform across the wavefront or invariant across a sub-cube's
-    samples excluded:
-      Philox4x32-10 block       17 products + 34 XOR          (ceil(d/2) blocks)
+    fma and conversions all issue at the full rate; v_rcp_f64 counts 4; a
+    three-input XOR is one v_bitop3_b32), with work that is uniform across the
+    wavefront or invariant across a sub-cube's samples excluded:
+      Philox4x32-10 block       17 products + 18 three-way XOR (ceil(d/2) blocks)
       per axis                  uniform 5, stratified coordinate 2, bin index
                                 and clamp 7, boundary address and width 2,
                                 point 2, Jacobian 2           = 20
@@ -60,7 +67,7 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
     d = int(prob["dim"])
     _, _, p = g_m_p
     kind = prob["integrand"]
-    philox = math.ceil(d / 2) * (17 + 34)
+    philox = math.ceil(d / 2) * PHILOX_BLOCK_OPS
     per_axis = 20 * d
     if kind == "const":
         f = 0
@@ -72,7 +79,39 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool) -> float:
     else:
         f = 3 * d + 20 + 2 * 21 + 2
     tail = 4 + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (19 + 5 * d) / p
+    if fp32:  # FP32-eval needs only the first ceil(d/4) blocks; the rest is counted alike
+        philox = math.ceil(d / 4) * PHILOX_BLOCK_OPS
     return float(philox + per_axis + f + tail)
+
+
+# The tables kernel's HBM traffic per launch comes from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs (scaled by a copy-kernel calibration) recorded in its
+# profile summary, together with a digest of the sources the kernel is built
+# from; it is reported only while those sources are unchanged.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "vsample_tables_d6_1e8.md")
+KERNEL_SOURCES = ("paper_2202_01753_amd/csrc/vsample.hpp", "paper_2202_01753_amd/csrc/vsample_tables.hip",
+                  "paper_2202_01753_amd/csrc/internal.hpp", "paper_2202_01753_amd/build.py")
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kind: str):
+    """HBM bytes per launch of the tables kernel ('fp64' or 'fp32') from the
+    profile summary, or None if absent or taken from other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-per-launch fp64=(\d+) fp32=(\d+) sources=([0-9a-f]{64})", text)
+    if not m or m.group(3) != kernel_sources_digest():
+        return None
+    return int(m.group(1) if kind == "fp64" else m.group(2))
 
 
 WORKLOADS = {
@@ -133,9 +172,7 @@ def bench_batch(args, M, W, torch):
     ops = 0.0
     for p in probs:
         gmp = M.shape(p["dim"], p["maxcalls"])
-        per = ops_per_sample(p, gmp, adjust=True)
-        if p["precision"] == "fp32":
-            per -= (math.ceil(p["dim"] / 2) - math.ceil(p["dim"] / 4)) * 51
+        per = ops_per_sample(p, gmp, adjust=True, fp32=p["precision"] == "fp32")
         ops += per * gmp[1] * gmp[2] * p["itmax"]
     ops *= args.steps
     line = _base_line(args, "batch_4096_mixed", calls / el, el / args.steps * 1e3,
@@ -251,16 +288,21 @@ def main():
     if args.workload == "serve":
         return bench_serve(args, M, W, torch)
     name, make = WORKLOADS[args.workload]
+    on_tables = args.workload == "tables"  # the workload the traffic profile was taken on
     prob = make(W, 1)
     bp = M.BoundProblem(prob, args.blocks, args.threads)
     ws = M.Workspace(bp)
+    M.prepare(prob, ws, bp=bp)
     gmp = M.shape(prob["dim"], prob["maxcalls"])
     calls_per_iter = gmp[1] * gmp[2]
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import closed_forms as CF
+    exact = CF.exact(prob)
 
     def step(seed):
         prob["seed"] = seed
         bp.s.seed = seed
-        return M.integrate(prob, ws=ws, bp=bp, timing=True)
+        return M.integrate(prob, ws=ws, bp=bp, timing=True, prepared=True)
 
     for w in range(args.warmup):
         step(1000 + w)
@@ -286,10 +328,11 @@ def main():
         pt = dict(prob, tau_rel=1e-3, precision=precision, seed=77)
         bpt = M.BoundProblem(pt, args.blocks, args.threads)
         wst = M.Workspace(bpt)
-        M.integrate(pt, ws=wst, bp=bpt)
+        M.prepare(pt, wst, bp=bpt)
+        M.integrate(pt, ws=wst, bp=bpt, prepared=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        r = M.integrate(pt, ws=wst, bp=bpt)
+        r = M.integrate(pt, ws=wst, bp=bpt, prepared=True)
         torch.cuda.synchronize()
         return r, time.perf_counter() - t
 
@@ -300,26 +343,34 @@ def main():
     p32 = dict(prob, precision="fp32")
     bp32 = M.BoundProblem(p32, args.blocks, args.threads)
     ws32 = M.Workspace(bp32)
+    M.prepare(p32, ws32, bp=bp32)
     for w in range(args.warmup):
         p32["seed"] = bp32.s.seed = 1000 + w
-        M.integrate(p32, ws=ws32, bp=bp32)
+        M.integrate(p32, ws=ws32, bp=bp32, prepared=True)
     torch.cuda.synchronize()
     res32 = []
     t2 = time.perf_counter()
     for k in range(args.steps):
         p32["seed"] = bp32.s.seed = 1 + k
-        res32.append(M.integrate(p32, ws=ws32, bp=bp32, timing=True))
+        res32.append(M.integrate(p32, ws=ws32, bp=bp32, timing=True, prepared=True))
     torch.cuda.synchronize()
     el32 = time.perf_counter() - t2
     rt32, tt32 = time_to_target("fp32")
     k32 = sum(r.sample_ms for r in res32) / sum(r.iterations for r in res32) / 1e3
+    ops32 = ops_per_sample(prob, gmp, adjust=prob["ita"] > 0, fp32=True) * calls_per_iter
     fp32_eval = {
         "value": sum(r.calls for r in res32) / el32, "unit": "samples/s",
         "ms_per_step": el32 / args.steps * 1e3, "kernel_samples_per_s": calls_per_iter / k32,
         "avg_launch_ms": k32 * 1e3,
+        "roofline": {"bound": "alu", "achieved": ops32 / k32 / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "TOP/s", "frac": ops32 / k32 / VALU_PEAK_OPS,
+                     "traffic": profiled_traffic("fp32") if on_tables else None,
+                     "kernel": "vsample_kernel (FP32-eval)",
+                     "ops_per_sample": ops32 / calls_per_iter},
         "time_to_1e-3": {"ms": tt32 * 1e3, "iterations": rt32.iterations,
                          "converged": rt32.converged, "estimate": rt32.estimate,
-                         "rel_error": rt32.error / abs(rt32.estimate)},
+                         "rel_error": rt32.error / abs(rt32.estimate),
+                         "true_rel_error": abs(rt32.estimate - exact) / abs(exact)},
         "vs_fp64_same_seed": {
             "rel_diff": (res32[0].estimate - results[0].estimate) / abs(results[0].estimate),
             "in_sigma": (res32[0].estimate - results[0].estimate)
@@ -342,9 +393,10 @@ def main():
         "config": {"workload": name, "dim": prob["dim"], "maxcalls": prob["maxcalls"],
                    "calls_per_iter": calls_per_iter, "nbins": prob["nbins"],
                    "itmax": prob["itmax"], "alpha": prob["alpha"],
-                   "step": "one full m-Cubes run (mc_integrate)"},
+                   "step": "one full m-Cubes run (mc_integrate_prepared, inputs resident)"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": profiled_traffic("fp64") if on_tables else None,
                      "kernel": "vsample_kernel", "avg_launch_ms": avg_launch_s * 1e3,
                      "ops_per_sample": ops / calls_per_iter,
                      "launch": {"blocks": r0.blocks, "threads": r0.threads,
@@ -352,8 +404,10 @@ def main():
         "kernel_samples_per_s": calls_per_iter / avg_launch_s,
         "finalize_ms_per_iter": fin_ms / launches,
         "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
-                         "estimate": rt.estimate, "rel_error": rt.error / abs(rt.estimate)},
-        "estimate": {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof},
+                         "estimate": rt.estimate, "rel_error": rt.error / abs(rt.estimate),
+                         "true_rel_error": abs(rt.estimate - exact) / abs(exact)},
+        "estimate": {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof,
+                     "exact": exact},
         "fp32_eval": fp32_eval,
     }
     if not args.no_cpu_baseline:

@@ -178,11 +178,23 @@ mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var
 mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
                        mc_result *out, double *h_iters, double *h_grid, mc_timing *timing);
 
+/* mc_integrate() on a workspace that mc_prepare() has already filled for the
+ * same problem (same integrand, parameters, tables, bounds and precision):
+ * nothing of the problem is uploaded again, so repeated runs, e.g. with other
+ * seeds or iteration counts, start with their inputs resident in device
+ * memory.  Arguments, results and errors as for mc_integrate().  On a
+ * workspace prepared for a different problem the result is meaningless (all
+ * accesses stay inside the workspace). */
+mc_status mc_integrate_prepared(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                                mc_result *out, double *h_iters, double *h_grid,
+                                mc_timing *timing);
+
 /* ---------------------------------------------------------------- batches and serving
  *
  * Many independent integrals advanced together.  Every step runs one sampling
  * pass (V-Sample or V-Sample-No-Adjust, per integral) of every active
- * integral in one persistent launch per precision present, merges each
+ * integral in one persistent launch per group present (precision, and
+ * whether the integral's LDS footprint limits workgroups per CU), merges each
  * integral's pieces in a fixed order, adjusts the grids of the integrals
  * still in their adjusting iterations on the device (the same steps as
  * mc_refine_grid, with the device library's pow and log), and then runs

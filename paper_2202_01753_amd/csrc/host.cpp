@@ -85,7 +85,7 @@ mc_status validate(const mc_problem *pr) {
     if (pr->one_d != 0 && pr->one_d != 1) return MC_EINVAL;
     if (is_fp32(pr) && g > (int64_t(1) << 24)) return MC_EINVAL;  // digits exact in float
     if (pr->nbins < 2 || pr->nbins > (1 << 20)) return MC_EINVAL;
-    if (lds_bytes_of(d, pr->nbins, true, is_fp32(pr)) > kLdsLimit) return MC_EINVAL;
+    if (lds_bytes_of(d, pr->nbins, true, is_fp32(pr)) > kLdsDynamicLimit) return MC_EINVAL;
     if (pr->itmax < 1 || pr->ita < 0 || pr->ita > pr->itmax) return MC_EINVAL;
     if (!(pr->alpha > 0.0) || !std::isfinite(pr->alpha)) return MC_EINVAL;
     if (!(pr->tau_rel >= 0.0) || !std::isfinite(pr->tau_rel)) return MC_EINVAL;

@@ -22,12 +22,20 @@ namespace host {
 constexpr int kDefaultThreads = 512;
 constexpr size_t kAlign = 256;
 constexpr size_t kLdsLimit = 160 * 1024;   // gfx950 LDS per workgroup
+// Dynamic LDS a sampling kernel may ask for: the workgroup's LDS less a
+// reserve for the kernels' static arrays (the reduction scratch, 520 bytes).
+constexpr size_t kLdsDynamicLimit = kLdsLimit - 1024;
 constexpr int64_t kTablesLen = 2 * kTableN * kTableN;
 constexpr int64_t kMaxIntervals = int64_t(1) << 30;  // g; keeps digit arithmetic in 32 bits
 
-#define HIP_TRY(expr)                               \
-    do {                                            \
-        if ((expr) != hipSuccess) return MC_EDEVICE; \
+// On failure the runtime's last-error state is cleared as well, so that the
+// caller's next HIP call does not see this error again.
+#define HIP_TRY(expr)                      \
+    do {                                   \
+        if ((expr) != hipSuccess) {        \
+            (void)hipGetLastError();       \
+            return MC_EDEVICE;             \
+        }                                  \
     } while (0)
 
 

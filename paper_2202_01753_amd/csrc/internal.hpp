@@ -68,8 +68,10 @@ hipError_t launch_clear_flag(uint32_t *flag, hipStream_t stream);
 // One integral of a batch.  a carries its constants, grid and table pointers,
 // lattice, iteration and whether this pass collects bin contributions (its
 // trace, partials and stride fields are unused).  out holds [I, var, flag, 0,
-// d*nb bin contributions] of the integral's latest pass; when refine is set,
-// the grid is adjusted on the device from that histogram after the pass.
+// d*nb bin contributions] of the integral's latest pass: the segments add
+// their bin contributions into it (zero at admission and after every bin
+// adjustment); when refine is set, the grid is adjusted on the device from
+// that histogram after the pass.
 struct BatchItem {
     SampleArgs a;
     double *grid;     // the integral's grid (a.grid, writable)
@@ -84,34 +86,50 @@ struct BatchSegment {
     int32_t item;       // integral (index into the items array)
     int32_t pad;
     int64_t t0, t1;     // sub-cubes [t0, t1)
-    int64_t hist_off;   // doubles into the segment-histogram buffer (collecting items)
 };
 
-// The device arrays of one batched step.  Workgroup w processes segments
-// [wg_first[w], wg_first[w+1]); an integral's segments are contiguous, in
-// [item_first[i], item_first[i+1]).
+// The device arrays of one batched step.  An integral's segments are
+// contiguous, [item_first[i], item_first[i+1]).  The workgroups of one
+// launch take the segments order[lo], order[lo+1], ... one at a time from the
+// launch's counter *queue (zero before the step) until it reaches hi.
 struct BatchArgs {
     const BatchItem *items;
     const BatchSegment *segs;
-    const int32_t *wg_first;
+    const int32_t *order;
     const int32_t *item_first;
     double *seg_tot;          // 4 doubles per segment
-    double *seg_hist;
     uint32_t *flags;          // per item, zero before the step
     double *res;              // per item: I, var, flag, 0 (packed for one read-back)
+    uint32_t *queue;          // this launch's segment counter
+    int32_t lo, hi;           // this launch's range of order
     int32_t n_items;
 };
 
-// Launches the batched sampling kernel of one precision over the segments of
-// its workgroups (wg_first points at this launch's workgroup table).
+// Admission of one integral into a batch: its per-axis constants are copied
+// from the step's upload into its block, its starting grid (Init-Bins,
+// uniform boundaries i/nb on every axis) is written there and its output
+// (totals and bin contributions) is cleared.
+struct AdmitRecord {
+    char *consts;         // destination of the constants in the integral's block
+    double *grid;         // destination of the d*(nb+1) starting boundaries
+    double *out;          // the integral's 4 + d*nb output doubles
+    int64_t src;          // byte offset of the constants in the upload (4-byte aligned)
+    int32_t const_words;  // 4-byte words of constants
+    int32_t dim, nb, pad;
+};
+hipError_t launch_admit(const AdmitRecord *recs, int n, const char *upload, hipStream_t stream);
+
+// Launches the batched sampling kernel of one precision over the segments
+// order[args.lo .. args.hi) (args.queue is this launch's counter).
 hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
                         const BatchArgs &args);
 const void *batch_kernel(bool fp32);
-// Merges every integral's segments in order into its out and res and clears its flag.
+// Merges every integral's segment totals in order into its out and res and clears its flag.
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream);
 // Adjust-Bin-Bounds on the device for n_axes (integral, axis) pairs
-// (axis_item[2a], axis_item[2a+1]): reads the integral's histogram from its out
-// and its boundaries from a.grid, writes the new ones to next_grid[integral].
+// (axis_item[2a], axis_item[2a+1]): reads the integral's histogram row from its
+// out (and clears it for the next collecting pass) and its boundaries from
+// a.grid, writes the new ones to next_grid[integral].
 hipError_t launch_batch_refine(const BatchItem *items, const int32_t *axis_item,
                                double *const *next_grid, int n_axes, int max_nb,
                                hipStream_t stream);

@@ -291,8 +291,14 @@ mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var
     return MC_OK;
 }
 
-mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
-                       mc_result *out, double *h_iters, double *h_grid, mc_timing *timing) {
+}  // extern "C"
+
+namespace {
+
+// Alg. 2 on a workspace; upload: copy the constants and tables first
+// (otherwise a previous mc_prepare() of the same problem left them there).
+mc_status integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream, bool upload,
+                    mc_result *out, double *h_iters, double *h_grid, mc_timing *timing) {
     if (!out) return MC_EINVAL;
     Geometry G;
     mc_status st = geometry(prob, &G);
@@ -300,8 +306,10 @@ mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void
     if (!d_ws || ws_bytes < G.total) return MC_EWORKSPACE;
     char *ws = static_cast<char *>(d_ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    st = prepare(prob, G, ws, s);
-    if (st != MC_OK) return st;
+    if (upload) {
+        st = prepare(prob, G, ws, s);
+        if (st != MC_OK) return st;
+    }
 
     const int d = prob->dim, nb = prob->nbins;
     std::vector<double> grid((size_t)d * (nb + 1)), buf(4 + (size_t)d * nb);
@@ -357,6 +365,21 @@ mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void
         timing->lds_bytes = (int32_t)(prob->ita > 0 ? G.lds_adj : G.lds_noadj);
     }
     return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_status mc_integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                       mc_result *out, double *h_iters, double *h_grid, mc_timing *timing) {
+    return integrate(prob, d_ws, ws_bytes, stream, true, out, h_iters, h_grid, timing);
+}
+
+mc_status mc_integrate_prepared(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                                mc_result *out, double *h_iters, double *h_grid,
+                                mc_timing *timing) {
+    return integrate(prob, d_ws, ws_bytes, stream, false, out, h_iters, h_grid, timing);
 }
 
 }  // extern "C"

@@ -6,15 +6,19 @@
 // [I, var, flag, 0, histogram]); a first-fit allocator hands it out, and an
 // integral is admitted only when its block and its share of the step area
 // fit ("admission by device memory").  Every step:
-//   1. admits queued integrals that fit (constants, tables and the initial
-//      grid are uploaded once);
-//   2. splits the active integrals' sub-cubes into contiguous segments of
-//      roughly equal work, one run of segments per workgroup, and uploads the
-//      step's small tables (items, segments, workgroup and item indices);
-//   3. runs one persistent batched sampling launch per precision present,
-//      the in-order merge of each integral's segments, and the bin adjustment
-//      of the integrals still adjusting — on the device, so grids and
-//      histograms stay resident;
+//   1. admits queued integrals that fit (tables are copied once; constants
+//      travel with the step's upload and the starting grid is written on the
+//      device);
+//   2. groups the active integrals by precision and by how many workgroups
+//      per CU their LDS footprint allows, splits each group's sub-cubes into
+//      contiguous segments of bounded work, orders them largest first, and
+//      uploads the step's small tables (items, segments, queue order and
+//      counters, item indices, admissions) in one copy;
+//   3. runs one persistent batched sampling launch per group present (its
+//      workgroups draw segments from a counter), the in-order merge of each
+//      integral's segment totals, and the bin adjustment of the integrals
+//      still adjusting — on the device, so grids and histograms stay
+//      resident;
 //   4. reads back 4 doubles per integral and runs Weighted-Estimates and
 //      Check-Convergence on the host; finished integrals release their block.
 #include <cmath>
@@ -76,6 +80,8 @@ struct Request {
     int64_t id = 0;
     mc_problem prob{};
     std::vector<double> params, tables, lo, hi;
+    std::vector<float> tables32;   // FP32-eval tables, kept until the request is released
+    std::vector<char> consts_img;  // per-axis constants in the device precision, until admitted
     int64_t g = 0, m = 0, p = 0;
     int32_t state = MC_REQ_QUEUED;
     mc_status status = MC_OK;
@@ -88,6 +94,7 @@ struct Request {
     int converged = 0;
     mc_result result{};
     double cost = 0;  // relative work per sub-cube (for the work split)
+    int group = 0;    // launch group of the current step
 };
 
 bool fp32_of(const Request &r) { return is_fp32(&r.prob); }
@@ -102,7 +109,7 @@ double cube_cost(const mc_problem &pr, int64_t p) {
     if (pr.integrand == MC_F_GAUSS_PRODUCT) f = 3.0 * d + 20;
     if (pr.integrand == MC_F_CORNER_PEAK) f = d + 16;
     if (pr.integrand == MC_F_GAUSS_TABLES) f = 3.0 * d + 64;
-    return (double)p * (51.0 * blocks + 25.0 * d + f + 10.0) + 20.0 + 5.0 * d;
+    return (double)p * (35.0 * blocks + 25.0 * d + f + 10.0) + 20.0 + 5.0 * d;
 }
 
 // Bytes of an integral's persistent block and the offsets inside it.
@@ -137,13 +144,30 @@ struct StepNeed {
 };
 
 struct StepLayout {
-    size_t items, item_first, flags, wg_first, segs, axis_item, next_grid, upload_end;
-    size_t res, seg_tot, seg_hist, total;
+    size_t items, item_first, flags, queue, order, segs, axis_item, next_grid, admit_recs, admit_data,
+        upload_end;
+    size_t res, seg_tot, total;
+    int64_t nseg;  // segments the layout has room for
 };
+
+// Launch groups per step: two precisions x {integrals whose LDS footprint
+// leaves the register-limited occupancy, the rest}.
+constexpr int kGroups = 4;
+// Upper bound of one integral's constants in bytes (kConstStride doubles per
+// axis at the batch's largest dimension).
+constexpr size_t kConstsMax = sizeof(double) * kConstStride * kBatchMaxDim;
+
+// Segments per workgroup of a launch: the queue balances the workgroups to
+// within about one segment.
+constexpr int kSegsPerWg = 8;
+// Sub-cubes a segment should at least hold (one per thread of a workgroup, twice).
+constexpr int64_t kMinSegCubes = 2 * kBatchBlock;
 
 StepLayout step_layout(const StepNeed &s, int gcap) {
     StepLayout L{};
-    const int64_t nseg = s.n + 2 * (int64_t)gcap;
+    // each group's split cuts at most kSegsPerWg * gcap (+1 for rounding) times
+    const int64_t nseg = s.n + kGroups * ((int64_t)kSegsPerWg * gcap + 1);
+    L.nseg = nseg;
     size_t off = 0;
     L.items = off;
     off = align_up(off + sizeof(BatchItem) * s.n);
@@ -151,21 +175,25 @@ StepLayout step_layout(const StepNeed &s, int gcap) {
     off = align_up(off + sizeof(int32_t) * (s.n + 1));
     L.flags = off;
     off = align_up(off + sizeof(uint32_t) * s.n);
-    L.wg_first = off;
-    off = align_up(off + sizeof(int32_t) * 2 * (gcap + 1));
+    L.queue = off;
+    off = align_up(off + sizeof(uint32_t) * kGroups);
+    L.order = off;
+    off = align_up(off + sizeof(int32_t) * nseg);
     L.segs = off;
     off = align_up(off + sizeof(BatchSegment) * nseg);
     L.axis_item = off;
     off = align_up(off + sizeof(int32_t) * 2 * s.sum_d);
     L.next_grid = off;
     off = align_up(off + sizeof(double *) * s.n);
+    L.admit_recs = off;
+    off = align_up(off + sizeof(AdmitRecord) * s.n);
+    L.admit_data = off;
+    off = align_up(off + kConstsMax * s.n);
     L.upload_end = off;
     L.res = off;
     off = align_up(off + sizeof(double) * 4 * s.n);
     L.seg_tot = off;
     off = align_up(off + sizeof(double) * 4 * nseg);
-    L.seg_hist = off;
-    off = align_up(off + sizeof(double) * (s.sum_dnb + 2 * (int64_t)gcap * s.max_dnb));
     L.total = off;
     return L;
 }
@@ -193,6 +221,9 @@ struct mc_server {
     std::deque<Request *> queue;
     std::vector<Request *> active;
     std::vector<int64_t> last_finished;  // ids finished in the last step
+    std::vector<Request *> admitted;     // admitted in this step, constants and grid pending
+    std::map<size_t, int> occ_cache[2];  // workgroups per CU by LDS bytes, per precision
+    int occ_full[2] = {0, 0};            // the register-limited occupancy, per precision
     StepNeed need;  // of the active set
     std::vector<char> staging;
     std::vector<double> res;
@@ -210,8 +241,28 @@ struct mc_server {
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         gcap = cus * 4;  // 256-thread workgroups: at most 4 per CU at the kernels' register use
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        for (int prec = 0; prec < 2; ++prec) {
+            HIP_TRY(allow_lds(batch_kernel(prec == 1), kLdsDynamicLimit));
+            int o = 0;
+            HIP_TRY(occupancy(prec, 0, &o));
+            occ_full[prec] = o;
+        }
         arena = std::make_unique<Arena>(arena_bytes);
         return MC_OK;
+    }
+
+    // Workgroups of the batched kernel of one precision that fit on a CU
+    // with the given dynamic LDS (cached: the kernel does not change).
+    mc_status occupancy(int prec, size_t lds, int *out) {
+        auto it = occ_cache[prec].find(lds);
+        if (it == occ_cache[prec].end()) {
+            int per_cu = 0;
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(prec == 1),
+                                                                 kBatchBlock, lds));
+            it = occ_cache[prec].emplace(lds, std::min(per_cu, gcap / cus)).first;
+        }
+        *out = it->second;
+        return *out >= 1 ? MC_OK : MC_EINVAL;
     }
 
     mc_status submit(const mc_problem *pr, int64_t *id) {
@@ -275,33 +326,28 @@ struct mc_server {
             r->off_grid[0] = off + og0;
             r->off_grid[1] = off + og1;
             r->off_out = off + oo;
-            const int d = r->prob.dim, nb = r->prob.nbins;
-            // constants, tables and the initial grid; host copies live in the Request
+            // tables now, from host memory the request keeps; constants and the
+            // starting grid with the step's upload (admit_kernel)
             const std::vector<double> c = axis_constants(&r->prob);
-            std::vector<double> grid((size_t)d * (nb + 1));
-            init_grid(d, nb, grid.data());
             if (fp32_of(*r)) {
                 const std::vector<float> c32(c.begin(), c.end());
-                HIP_TRY(hipMemcpyAsync(ws + r->off_consts, c32.data(), sizeof(float) * c32.size(),
-                                       hipMemcpyHostToDevice, stream));
+                r->consts_img.assign(reinterpret_cast<const char *>(c32.data()),
+                                     reinterpret_cast<const char *>(c32.data() + c32.size()));
                 if (!r->tables.empty()) {
-                    const std::vector<float> t32(r->tables.begin(), r->tables.end());
-                    HIP_TRY(hipMemcpyAsync(ws + r->off_tables, t32.data(), sizeof(float) * t32.size(),
-                                           hipMemcpyHostToDevice, stream));
-                    HIP_TRY(hipStreamSynchronize(stream));
+                    r->tables32.assign(r->tables.begin(), r->tables.end());
+                    HIP_TRY(hipMemcpyAsync(ws + r->off_tables, r->tables32.data(),
+                                           sizeof(float) * r->tables32.size(), hipMemcpyHostToDevice,
+                                           stream));
                 }
-                HIP_TRY(hipStreamSynchronize(stream));
             } else {
-                HIP_TRY(hipMemcpyAsync(ws + r->off_consts, c.data(), sizeof(double) * c.size(),
-                                       hipMemcpyHostToDevice, stream));
+                r->consts_img.assign(reinterpret_cast<const char *>(c.data()),
+                                     reinterpret_cast<const char *>(c.data() + c.size()));
                 if (!r->tables.empty())
                     HIP_TRY(hipMemcpyAsync(ws + r->off_tables, r->tables.data(),
                                            sizeof(double) * r->tables.size(), hipMemcpyHostToDevice,
                                            stream));
             }
-            HIP_TRY(hipMemcpyAsync(ws + r->off_grid[0], grid.data(), sizeof(double) * grid.size(),
-                                   hipMemcpyHostToDevice, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            admitted.push_back(r);
             r->cur = 0;
             r->state = MC_REQ_RUNNING;
             queue.pop_front();
@@ -311,11 +357,12 @@ struct mc_server {
         return MC_OK;
     }
 
-    // Splits the items [first, last) of one precision into segments of
-    // roughly equal work over G workgroups; appends to segs and wg_first.
-    void split(const std::vector<Request *> &items, int first, int last, int G,
-               std::vector<BatchSegment> &segs, std::vector<int32_t> &wg_first,
-               std::vector<int32_t> &item_first, int64_t &hist_cursor) {
+    // Splits the items [first, last) of one launch group into segments: the
+    // group's work is cut into `parts` equal shares and every item into the
+    // pieces the cuts leave (items smaller than a share stay whole).
+    // Appends to segs; item_first[i] is set to the item's first segment.
+    void split(const std::vector<Request *> &items, int first, int last, int64_t parts,
+               std::vector<BatchSegment> &segs, std::vector<int32_t> &item_first) {
         double W = 0.0;
         std::vector<double> start(last - first + 1);
         for (int i = first; i < last; ++i) {
@@ -323,30 +370,20 @@ struct mc_server {
             W += (double)items[i]->m * items[i]->cost;
         }
         start[last - first] = W;
-        auto bound = [&](int i, int k) -> int64_t {
-            const double x = W * (double)k / (double)G;
-            const double c = std::llround((x - start[i - first]) / items[i]->cost);
-            return std::min<int64_t>(std::max<int64_t>((int64_t)c, 0), items[i]->m);
-        };
-        int i0 = first;
-        for (int k = 0; k < G; ++k) {
-            wg_first.push_back((int32_t)segs.size());
-            const double x0 = W * (double)k / (double)G, x1 = W * (double)(k + 1) / (double)G;
-            while (i0 < last && start[i0 + 1 - first] <= x0 && bound(i0, k) >= items[i0]->m) ++i0;
-            for (int i = i0; i < last && start[i - first] <= x1; ++i) {
-                const int64_t t0 = bound(i, k), t1 = bound(i, k + 1);
-                if (t1 <= t0) continue;
-                if (item_first[i] < 0) item_first[i] = (int32_t)segs.size();
-                BatchSegment sg{};
-                sg.item = i;
-                sg.t0 = t0;
-                sg.t1 = t1;
-                if (items[i]->it < items[i]->prob.ita) {
-                    sg.hist_off = hist_cursor;
-                    hist_cursor += dnb(*items[i]);
-                }
-                segs.push_back(sg);
+        const double share = W / (double)parts;
+        for (int i = first; i < last; ++i) {
+            const Request &r = *items[i];
+            item_first[i] = (int32_t)segs.size();
+            // cuts at multiples of share inside the item, in sub-cube units
+            const double a = start[i - first], b = start[i + 1 - first];
+            int64_t t0 = 0;
+            for (double x = std::ceil(a / share) * share; x < b; x += share) {
+                const int64_t t = std::min<int64_t>((int64_t)std::llround((x - a) / r.cost), r.m);
+                if (t <= t0) continue;
+                segs.push_back(BatchSegment{i, 0, t0, t});
+                t0 = t;
             }
+            if (t0 < r.m) segs.push_back(BatchSegment{i, 0, t0, r.m});
         }
     }
 
@@ -357,11 +394,19 @@ struct mc_server {
         if (st != MC_OK) return st;
         if (active.empty()) return MC_OK;
         const auto t_start = std::chrono::steady_clock::now();
-        // FP64 integrals first, then FP32: one launch per precision present
-        std::stable_partition(active.begin(), active.end(), [](Request *r) { return !fp32_of(*r); });
+        // launch groups: precision, then whether the integral's LDS footprint
+        // still allows the kernel's register-limited workgroups per CU
+        for (Request *r : active) {
+            const int prec = fp32_of(*r) ? 1 : 0;
+            const size_t lds = lds_bytes_of(r->prob.dim, r->prob.nbins, r->it < r->prob.ita, prec == 1);
+            int o = 0;
+            st = occupancy(prec, lds, &o);
+            if (st != MC_OK) return st;
+            r->group = 2 * prec + (o < occ_full[prec] ? 1 : 0);
+        }
+        std::stable_sort(active.begin(), active.end(),
+                         [](const Request *x, const Request *y) { return x->group < y->group; });
         const int n = (int)active.size();
-        int n64 = 0;
-        while (n64 < n && !fp32_of(*active[n64])) ++n64;
 
         char *step_base = ws + arena_bytes;
         const StepLayout L = step_layout(need, gcap);
@@ -371,7 +416,8 @@ struct mc_server {
         double **next_grid = reinterpret_cast<double **>(staging.data() + L.next_grid);
         int32_t *axis_item = reinterpret_cast<int32_t *>(staging.data() + L.axis_item);
         int n_axes = 0, max_nb = 2;
-        size_t lds[2] = {0, 0};
+        size_t lds[kGroups] = {};
+        int first[kGroups + 1] = {};
         for (int i = 0; i < n; ++i) {
             Request *r = active[i];
             const bool adjust = r->it < r->prob.ita;
@@ -393,49 +439,81 @@ struct mc_server {
                 }
                 max_nb = std::max(max_nb, r->prob.nbins);
             }
-            const int grp = fp32_of(*r) ? 1 : 0;
-            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, grp == 1));
+            const int grp = r->group;
+            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, grp >= 2));
+            first[grp + 1] = i + 1;
         }
-        // work split per precision group
+        for (int grp = 1; grp <= kGroups; ++grp) first[grp] = std::max(first[grp], first[grp - 1]);
+        // work split per group, each group one launch filling the GPU; its
+        // segments go to the queue largest first
         std::vector<BatchSegment> segs;
-        std::vector<int32_t> wg_first, item_first(n, -1);
-        int64_t hist_cursor = 0;
-        int G[2] = {0, 0};
-        for (int grp = 0; grp < 2; ++grp) {
-            const int first = grp == 0 ? 0 : n64, last = grp == 0 ? n64 : n;
-            if (first == last) continue;
-            const void *fn = batch_kernel(grp == 1);
-            HIP_TRY(allow_lds(fn, lds[grp]));
+        std::vector<int32_t> item_first(n, -1), order;
+        int G[kGroups] = {}, seg_lo[kGroups + 1] = {};
+        for (int grp = 0; grp < kGroups; ++grp) {
+            seg_lo[grp] = (int)segs.size();
+            if (first[grp] == first[grp + 1]) continue;
             int per_cu = 0;
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchBlock, lds[grp]));
-            if (per_cu < 1) return MC_EINVAL;
-            G[grp] = std::min(per_cu * cus, gcap);
-            split(active, first, last, G[grp], segs, wg_first, item_first, hist_cursor);
-            wg_first.push_back((int32_t)segs.size());
+            st = occupancy(grp >= 2 ? 1 : 0, lds[grp], &per_cu);
+            if (st != MC_OK) return st;
+            G[grp] = per_cu * cus;
+            int64_t cubes = 0;
+            for (int i = first[grp]; i < first[grp + 1]; ++i) cubes += active[i]->m;
+            const int64_t parts =
+                std::max<int64_t>(1, std::min<int64_t>((int64_t)kSegsPerWg * G[grp], cubes / kMinSegCubes));
+            split(active, first[grp], first[grp + 1], parts, segs, item_first);
+            const size_t o0 = order.size();
+            for (int k = seg_lo[grp]; k < (int)segs.size(); ++k) order.push_back(k);
+            auto work = [&](int32_t k) {
+                return (double)(segs[k].t1 - segs[k].t0) * active[segs[k].item]->cost;
+            };
+            std::stable_sort(order.begin() + o0, order.end(),
+                             [&](int32_t x, int32_t y) { return work(x) > work(y); });
         }
+        seg_lo[kGroups] = (int)segs.size();
+        if ((int64_t)segs.size() > L.nseg) return MC_EINVAL;  // cannot happen: the layout's bound
         for (int i = 0; i < n; ++i) item_first_h[i] = item_first[i];
         item_first_h[n] = (int32_t)segs.size();
         std::memcpy(staging.data() + L.segs, segs.data(), sizeof(BatchSegment) * segs.size());
-        std::memcpy(staging.data() + L.wg_first, wg_first.data(), sizeof(int32_t) * wg_first.size());
-        HIP_TRY(hipMemcpyAsync(step_base, staging.data(), L.upload_end, hipMemcpyHostToDevice, stream));
+        std::memcpy(staging.data() + L.order, order.data(), sizeof(int32_t) * order.size());
+        // the queue counters are zero: the staging buffer is cleared every step
+        // admissions of this step: constants into the upload, records for admit_kernel
+        AdmitRecord *recs = reinterpret_cast<AdmitRecord *>(staging.data() + L.admit_recs);
+        size_t adm_off = L.admit_data;
+        for (size_t k = 0; k < admitted.size(); ++k) {
+            Request *r = admitted[k];
+            std::memcpy(staging.data() + adm_off, r->consts_img.data(), r->consts_img.size());
+            AdmitRecord &rec = recs[k];
+            rec.consts = ws + r->off_consts;
+            rec.grid = reinterpret_cast<double *>(ws + r->off_grid[0]);
+            rec.out = reinterpret_cast<double *>(ws + r->off_out);
+            rec.src = (int64_t)adm_off;
+            rec.const_words = (int32_t)(r->consts_img.size() / 4);
+            rec.dim = r->prob.dim;
+            rec.nb = r->prob.nbins;
+            adm_off += kConstsMax;
+            std::vector<char>().swap(r->consts_img);
+        }
+        HIP_TRY(hipMemcpyAsync(step_base, staging.data(), adm_off, hipMemcpyHostToDevice, stream));
+        HIP_TRY(launch_admit(reinterpret_cast<const AdmitRecord *>(step_base + L.admit_recs),
+                             (int)admitted.size(), step_base, stream));
+        admitted.clear();
 
         BatchArgs A{};
         A.items = reinterpret_cast<const BatchItem *>(step_base + L.items);
         A.segs = reinterpret_cast<const BatchSegment *>(step_base + L.segs);
         A.item_first = reinterpret_cast<const int32_t *>(step_base + L.item_first);
         A.seg_tot = reinterpret_cast<double *>(step_base + L.seg_tot);
-        A.seg_hist = reinterpret_cast<double *>(step_base + L.seg_hist);
+        A.order = reinterpret_cast<const int32_t *>(step_base + L.order);
         A.flags = reinterpret_cast<uint32_t *>(step_base + L.flags);
         A.res = reinterpret_cast<double *>(step_base + L.res);
         A.n_items = n;
-        const int32_t *wg_dev = reinterpret_cast<const int32_t *>(step_base + L.wg_first);
         HIP_TRY(hipEventRecord(ev[0], stream));
-        int wg_base = 0;
-        for (int grp = 0; grp < 2; ++grp) {
+        for (int grp = 0; grp < kGroups; ++grp) {
             if (!G[grp]) continue;
-            A.wg_first = wg_dev + wg_base;
-            HIP_TRY(launch_batch(grp == 1, G[grp], kBatchBlock, lds[grp], stream, A));
-            wg_base += G[grp] + 1;
+            A.queue = reinterpret_cast<uint32_t *>(step_base + L.queue) + grp;
+            A.lo = seg_lo[grp];
+            A.hi = seg_lo[grp + 1];
+            HIP_TRY(launch_batch(grp >= 2, G[grp], kBatchBlock, lds[grp], stream, A));
         }
         HIP_TRY(hipEventRecord(ev[1], stream));
         HIP_TRY(launch_batch_finalize(A, stream));

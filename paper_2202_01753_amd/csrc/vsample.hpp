@@ -27,15 +27,22 @@ namespace mcubes {
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon et al., SC'11: ten rounds of two 32x32->64 products, with the key
 // advanced by the Weyl constants between rounds.  The key is uniform across
-// the wavefront, so its schedule stays in scalar registers.
+// the wavefront, so its schedule stays in scalar registers.  Each round's two
+// three-way XORs are single v_bitop3_b32 instructions (truth table 0x96 is
+// a ^ b ^ c); in the first round the counter words x1, x3 are uniform or fixed
+// per sub-cube, so there the compiler folds their XOR with the key instead.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32_t &x2,
                                               uint32_t &x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x0;
         const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
-        const uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
-        const uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        const uint32_t y0 = r == 0 ? (uint32_t)(pb >> 32) ^ (x1 ^ k0) : xor3((uint32_t)(pb >> 32), x1, k0);
+        const uint32_t y2 = r == 0 ? (uint32_t)(pa >> 32) ^ (x3 ^ k1) : xor3((uint32_t)(pa >> 32), x3, k1);
         x1 = (uint32_t)pb;
         x3 = (uint32_t)pa;
         x0 = y0;

@@ -1,13 +1,16 @@
 // Batched V-Sample: the sampling passes of many independent integrals (any
 // mix of integrand, dimension and bin count) in one persistent launch.  The
 // host splits the active integrals' sub-cubes into contiguous segments of
-// roughly equal work and gives each workgroup a run of consecutive segments;
-// for each segment the workgroup loads that integral's constants and grid
-// into LDS, samples the segment's cubes with the same per-cube code as the
-// single-integral kernel, and writes the segment's totals and histogram.
-// A second kernel merges every integral's segments in order, and a third
-// adjusts the grids of the integrals still in their adjusting iterations, on
-// the device, so that grids and histograms never leave it.
+// bounded work and orders them largest first; the workgroups take segments
+// from a shared counter until none is left, so they finish together whatever
+// the actual cost of each integrand.  For each segment the workgroup loads
+// that integral's constants and grid into LDS, samples the segment's cubes
+// with the same per-cube code as the single-integral kernel, writes the
+// segment's totals to its own slot and adds its LDS histogram into the
+// integral's.  A second kernel merges every integral's segment totals in
+// order (so the totals do not depend on which workgroup took which segment),
+// and a third adjusts the grids of the integrals still in their adjusting
+// iterations, on the device, so that grids and histograms never leave it.
 #include "vsample.hpp"
 
 namespace mcubes {
@@ -43,8 +46,14 @@ __device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegm
     }
     block_totals(sI, cI, sV, cV, bad, B.seg_tot + 4 * (size_t)si, B.flags + sg.item);
     if (a.hist) {
-        double *dst = B.seg_hist + sg.hist_off;
-        for (int i = threadIdx.x; i < D * a.nb; i += blockDim.x) dst[i] = v.hist[i];
+        // into the integral's histogram in device memory (ordinary device
+        // allocations, so the hardware FP64 atomic add applies); bins this
+        // segment never reached are skipped
+        double *dst = B.items[sg.item].out + 4;
+        for (int i = threadIdx.x; i < D * a.nb; i += blockDim.x) {
+            const double h = v.hist[i];
+            if (h != 0.0) unsafeAtomicAdd(dst + i, h);
+        }
     }
     __syncthreads();  // LDS is reused by the next segment
 }
@@ -61,8 +70,15 @@ template <bool F32>
 __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3)))
 vsample_batch_kernel(const BatchArgs B) {
     extern __shared__ double lds[];
-    const int first = B.wg_first[blockIdx.x], last = B.wg_first[blockIdx.x + 1];
-    for (int si = first; si < last; ++si) {
+    __shared__ int32_t next;
+    for (;;) {
+        // every workgroup leaves once the counter has passed hi
+        if (threadIdx.x == 0) next = B.lo + (int32_t)atomicAdd(B.queue, 1u);
+        __syncthreads();
+        const int32_t q = next;
+        __syncthreads();
+        if (q >= B.hi) break;
+        const int si = B.order[q];
         const BatchSegment sg = B.segs[si];
         const SampleArgs &a = B.items[sg.item].a;
         switch (a.kind) {
@@ -81,35 +97,26 @@ vsample_batch_kernel(const BatchArgs B) {
 
 constexpr int kFinThreads = 256;
 
-// One block per integral: totals and (collecting integrals) each bin summed
-// over the integral's segments in order, TwoSum-compensated.
+// One thread per integral: its segment totals summed in segment order,
+// TwoSum-compensated.
 __global__ void __launch_bounds__(kFinThreads) batch_finalize_kernel(const BatchArgs B) {
-    const int item = blockIdx.x;
+    const int item = blockIdx.x * kFinThreads + threadIdx.x;
+    if (item >= B.n_items) return;
     const BatchItem &it = B.items[item];
     const int s0 = B.item_first[item], s1 = B.item_first[item + 1];
     double *o = it.out;
-    if (threadIdx.x == 0) {
-        double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
-        for (int s = s0; s < s1; ++s) {
-            const double *q = B.seg_tot + 4 * (size_t)s;
-            two_sum_merge(sI, cI, q[0], q[1]);
-            two_sum_merge(sV, cV, q[2], q[3]);
-        }
-        const double flag = B.flags[item] ? 1.0 : 0.0;
-        o[0] = B.res[4 * item] = sI + cI;
-        o[1] = B.res[4 * item + 1] = sV + cV;
-        o[2] = B.res[4 * item + 2] = flag;
-        o[3] = B.res[4 * item + 3] = 0.0;
-        B.flags[item] = 0u;
+    double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const double *q = B.seg_tot + 4 * (size_t)s;
+        two_sum_merge(sI, cI, q[0], q[1]);
+        two_sum_merge(sV, cV, q[2], q[3]);
     }
-    if (it.a.hist) {
-        const int nh = (it.a.kind & 31) * it.a.nb;
-        for (int b = threadIdx.x; b < nh; b += kFinThreads) {
-            double s = 0.0, c = 0.0;
-            for (int q = s0; q < s1; ++q) two_sum_merge(s, c, B.seg_hist[B.segs[q].hist_off + b], 0.0);
-            o[4 + b] = s + c;
-        }
-    }
+    const double flag = B.flags[item] ? 1.0 : 0.0;
+    o[0] = B.res[4 * item] = sI + cI;
+    o[1] = B.res[4 * item + 1] = sV + cV;
+    o[2] = B.res[4 * item + 2] = flag;
+    o[3] = B.res[4 * item + 3] = 0.0;
+    B.flags[item] = 0u;
 }
 
 // Adjust-Bin-Bounds on the device, one block per (integral, axis): three-
@@ -128,7 +135,7 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
     const int item = axis_item[2 * ax], j = axis_item[2 * ax + 1];
     const BatchItem &it = items[item];
     const int nb = it.a.nb;
-    const double *C = it.out + 4 + (size_t)j * nb;
+    double *C = it.out + 4 + (size_t)j * nb;
     const double *B = it.a.grid + (size_t)j * (nb + 1);
     double *Bn = next_grid[item] + (size_t)j * (nb + 1);
     const double alpha = it.alpha;
@@ -140,6 +147,8 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
         r[i] = s;
     }
     __syncthreads();
+    // the row is read: clear it for the next collecting pass
+    for (int i = threadIdx.x; i < nb; i += kRefThreads) C[i] = 0.0;
     __shared__ double total_s;
     __shared__ int usable;
     if (threadIdx.x == 0) {
@@ -190,7 +199,29 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
         for (int i = 0; i <= nb; ++i) Bn[(size_t)c * (nb + 1) + i] = Bn[i];
 }
 
+// One block per admitted integral: constants from the upload, then the
+// uniform grid B_j[i] = i/nb (one correctly rounded division, as on the host).
+constexpr int kAdmitThreads = 256;
+
+__global__ void __launch_bounds__(kAdmitThreads)
+admit_kernel(const AdmitRecord *recs, const char *upload) {
+    const AdmitRecord r = recs[blockIdx.x];
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(upload + r.src);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(r.consts);
+    for (int i = threadIdx.x; i < r.const_words; i += kAdmitThreads) dst[i] = src[i];
+    const int row = r.nb + 1;
+    const double nbd = (double)r.nb;
+    for (int i = threadIdx.x; i < r.dim * row; i += kAdmitThreads) r.grid[i] = (double)(i % row) / nbd;
+    for (int i = threadIdx.x; i < 4 + r.dim * r.nb; i += kAdmitThreads) r.out[i] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_admit(const AdmitRecord *recs, int n, const char *upload, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(admit_kernel, dim3(n), dim3(kAdmitThreads), 0, stream, recs, upload);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
                         const BatchArgs &args) {
@@ -209,7 +240,8 @@ const void *batch_kernel(bool fp32) {
 }
 
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3(args.n_items), dim3(kFinThreads), 0, stream, args);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3((args.n_items + kFinThreads - 1) / kFinThreads),
+                       dim3(kFinThreads), 0, stream, args);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
            "mc_weighted_estimate",
-           "mc_integrate", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
+           "mc_integrate", "mc_integrate_prepared", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
            "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
            "mc_server_release",
            "mc_server_stats", "mc_server_destroy")
@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
             "mc_weighted_estimate": ([C.c_int32, dp, dp, dp], C.c_int32),
             "mc_integrate": ([P, vp, sz, vp, C.POINTER(Result), dp, dp, C.POINTER(Timing)],
                              C.c_int32),
+            "mc_integrate_prepared": ([P, vp, sz, vp, C.POINTER(Result), dp, dp,
+                                       C.POINTER(Timing)], C.c_int32),
             "mc_batch_workspace_bytes": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
             "mc_batch_integrate": ([P, C.c_int32, vp, sz, vp, C.POINTER(Result),
                                     C.POINTER(C.c_int32), C.POINTER(BatchStats)], C.c_int32),
@@ -253,17 +255,29 @@ class IntegrationResult:
     lds_bytes: int = 0
 
 
+def prepare(prob: dict, ws: Workspace, stream=None, bp: BoundProblem | None = None) -> None:
+    """mc_prepare: uploads the problem's constants and tables into ws."""
+    bp = bp or BoundProblem(prob)
+    _check(lib().mc_prepare(bp.ref, ws.ptr, ws.nbytes, _stream(stream)), "mc_prepare")
+
+
 def integrate(prob: dict, ws: Workspace | None = None, stream=None, blocks: int = 0,
-              threads: int = 0, timing: bool = False, bp: BoundProblem | None = None):
+              threads: int = 0, timing: bool = False, bp: BoundProblem | None = None,
+              prepared: bool = False):
+    """mc_integrate, or mc_integrate_prepared when prepared is set (ws then
+    already holds this problem's constants and tables, see prepare())."""
     bp = bp or BoundProblem(prob, blocks, threads)
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the prepared workspace")
     ws = ws or Workspace(bp)
     d, nb, itmax = int(prob["dim"]), int(prob["nbins"]), int(prob["itmax"])
     res = Result()
     iters = np.zeros(2 * itmax)
     grid = np.zeros(d * (nb + 1))
     tm = Timing() if timing else None
-    _check(lib().mc_integrate(bp.ref, ws.ptr, ws.nbytes, _stream(stream), C.byref(res), _dp(iters),
-                              _dp(grid), C.byref(tm) if tm is not None else None), "mc_integrate")
+    fn = lib().mc_integrate_prepared if prepared else lib().mc_integrate
+    _check(fn(bp.ref, ws.ptr, ws.nbytes, _stream(stream), C.byref(res), _dp(iters),
+              _dp(grid), C.byref(tm) if tm is not None else None), "mc_integrate")
     k = res.iterations
     out = IntegrationResult(res.estimate, res.error, res.chi2_dof, k, bool(res.converged),
                             res.calls, iters[0:2 * k:2].copy(), iters[1:2 * k:2].copy(), grid)

@@ -131,6 +131,8 @@ def test_invalid_problems_rejected_before_device_work(name, prob, kw):
     res = M.Result(estimate=7.0)
     code = M.lib().mc_integrate(bp.ref, None, 0, None, C.byref(res), None, None, None)
     assert code == M.EINVAL and res.estimate == 7.0
+    code = M.lib().mc_integrate_prepared(bp.ref, None, 0, None, C.byref(res), None, None, None)
+    assert code == M.EINVAL and res.estimate == 7.0
 
 
 def test_null_arguments_rejected():

@@ -212,6 +212,26 @@ def test_deterministic_repeat():
     assert np.allclose(a["hist"], b["hist"], rtol=TOL, atol=0)
 
 
+def test_integrate_prepared_matches_integrate():
+    """mc_integrate_prepared on a workspace filled once by mc_prepare gives
+    mc_integrate's results run after run, for both precisions (to rounding:
+    the LDS histogram atomics make bin sums, and so later grids, order-
+    dependent in the last ulp)."""
+    for precision in ("fp64", "fp32"):
+        prob = W.config_tables(seed=8, maxcalls=1_000_000, itmax=4, precision=precision)
+        bp = M.BoundProblem(prob)
+        ws = M.Workspace(bp)
+        M.prepare(prob, ws, bp=bp)
+        for seed in (3, 4):
+            prob["seed"] = bp.s.seed = seed
+            a = M.integrate(prob, ws=ws, bp=bp, prepared=True)
+            b = M.integrate(prob)
+            assert a.iterations == b.iterations
+            assert a.estimate == pytest.approx(b.estimate, rel=TOL, abs=0)
+            assert a.error == pytest.approx(b.error, rel=1e-9, abs=0)
+            assert np.allclose(a.grid, b.grid, rtol=0, atol=1e-12)
+
+
 # ---------------------------------------------------------------- full-size configurations
 
 def _sampled_full_size(prob, windows, n=1500):
