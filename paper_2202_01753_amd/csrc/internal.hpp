@@ -10,7 +10,8 @@ namespace mcubes {
 constexpr int kMaxDim = 16;
 constexpr int kTableN = 256;
 constexpr int kMaxBlock = 1024;
-constexpr int kBatchBlock = 256;     // threads per workgroup of the batched kernel
+constexpr int kBatchBlock = 256;     // threads per workgroup of the batched kernel (or twice that)
+constexpr int kBatchMaxBlock = 512;
 constexpr int kBatchMaxDim = 10;     // dimensions the batched kernel supports
 
 // Everything the sampling kernel needs, passed by value so that the per-axis
@@ -119,11 +120,13 @@ struct AdmitRecord {
 };
 hipError_t launch_admit(const AdmitRecord *recs, int n, const char *upload, hipStream_t stream);
 
-// Launches the batched sampling kernel of one precision over the segments
-// order[args.lo .. args.hi) (args.queue is this launch's counter).
-hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
-                        const BatchArgs &args);
-const void *batch_kernel(bool fp32);
+// Launches the batched sampling kernel of one precision and integrand family
+// (tables: the Gaussian-times-tables integrand; otherwise the closed-form
+// ones) over the segments order[args.lo .. args.hi) (args.queue is this
+// launch's counter).  threads is kBatchBlock or kBatchMaxBlock.
+hipError_t launch_batch(bool fp32, bool tables, int blocks, int threads, size_t lds_bytes,
+                        hipStream_t stream, const BatchArgs &args);
+const void *batch_kernel(bool fp32, bool tables);
 // Merges every integral's segment totals in order into its out and res and clears its flag.
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream);
 // Adjust-Bin-Bounds on the device for n_axes (integral, axis) pairs

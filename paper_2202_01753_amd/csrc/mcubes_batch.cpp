@@ -150,9 +150,14 @@ struct StepLayout {
     int64_t nseg;  // segments the layout has room for
 };
 
-// Launch groups per step: two precisions x {integrals whose LDS footprint
-// leaves the register-limited occupancy, the rest}.
-constexpr int kGroups = 4;
+// Batched kernels: precision x integrand family (closed forms, tables).
+constexpr int kKernels = 4;
+int kernel_of(const Request &r) {
+    return 2 * (fp32_of(r) ? 1 : 0) + (r.prob.integrand == MC_F_GAUSS_TABLES ? 1 : 0);
+}
+// Launch groups per step: kernel x {integrals whose LDS footprint leaves the
+// kernel's register-limited occupancy, the rest}.
+constexpr int kGroups = 2 * kKernels;
 // Upper bound of one integral's constants in bytes (kConstStride doubles per
 // axis at the batch's largest dimension).
 constexpr size_t kConstsMax = sizeof(double) * kConstStride * kBatchMaxDim;
@@ -161,7 +166,7 @@ constexpr size_t kConstsMax = sizeof(double) * kConstStride * kBatchMaxDim;
 // within about one segment.
 constexpr int kSegsPerWg = 8;
 // Sub-cubes a segment should at least hold (one per thread of a workgroup, twice).
-constexpr int64_t kMinSegCubes = 2 * kBatchBlock;
+constexpr int64_t kMinSegCubes = 2 * kBatchMaxBlock;
 
 StepLayout step_layout(const StepNeed &s, int gcap) {
     StepLayout L{};
@@ -222,8 +227,8 @@ struct mc_server {
     std::vector<Request *> active;
     std::vector<int64_t> last_finished;  // ids finished in the last step
     std::vector<Request *> admitted;     // admitted in this step, constants and grid pending
-    std::map<size_t, int> occ_cache[2];  // workgroups per CU by LDS bytes, per precision
-    int occ_full[2] = {0, 0};            // the register-limited occupancy, per precision
+    std::map<std::pair<size_t, int>, int> occ_cache[kKernels];  // workgroups per CU by (LDS, threads)
+    int occ_full[kKernels] = {};  // the register-limited occupancy (256-thread workgroups)
     StepNeed need;  // of the active set
     std::vector<char> staging;
     std::vector<double> res;
@@ -241,25 +246,25 @@ struct mc_server {
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         gcap = cus * 4;  // 256-thread workgroups: at most 4 per CU at the kernels' register use
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-        for (int prec = 0; prec < 2; ++prec) {
-            HIP_TRY(allow_lds(batch_kernel(prec == 1), kLdsDynamicLimit));
-            int o = 0;
-            HIP_TRY(occupancy(prec, 0, &o));
-            occ_full[prec] = o;
+        for (int k = 0; k < kKernels; ++k) {
+            HIP_TRY(allow_lds(batch_kernel(k >= 2, k % 2 == 1), kLdsDynamicLimit));
+            mc_status st = occupancy(k, kBatchBlock, 0, &occ_full[k]);
+            if (st != MC_OK) return st;
         }
         arena = std::make_unique<Arena>(arena_bytes);
         return MC_OK;
     }
 
-    // Workgroups of the batched kernel of one precision that fit on a CU
-    // with the given dynamic LDS (cached: the kernel does not change).
-    mc_status occupancy(int prec, size_t lds, int *out) {
-        auto it = occ_cache[prec].find(lds);
-        if (it == occ_cache[prec].end()) {
+    // Workgroups of a batched kernel that fit on a CU with the given
+    // workgroup size and dynamic LDS (cached: the kernels do not change).
+    mc_status occupancy(int kern, int threads, size_t lds, int *out) {
+        const auto key = std::make_pair(lds, threads);
+        auto it = occ_cache[kern].find(key);
+        if (it == occ_cache[kern].end()) {
             int per_cu = 0;
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(prec == 1),
-                                                                 kBatchBlock, lds));
-            it = occ_cache[prec].emplace(lds, std::min(per_cu, gcap / cus)).first;
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, batch_kernel(kern >= 2, kern % 2 == 1), threads, lds));
+            it = occ_cache[kern].emplace(key, std::min(per_cu, gcap / cus)).first;
         }
         *out = it->second;
         return *out >= 1 ? MC_OK : MC_EINVAL;
@@ -394,15 +399,15 @@ struct mc_server {
         if (st != MC_OK) return st;
         if (active.empty()) return MC_OK;
         const auto t_start = std::chrono::steady_clock::now();
-        // launch groups: precision, then whether the integral's LDS footprint
+        // launch groups: the kernel, then whether the integral's LDS footprint
         // still allows the kernel's register-limited workgroups per CU
         for (Request *r : active) {
-            const int prec = fp32_of(*r) ? 1 : 0;
-            const size_t lds = lds_bytes_of(r->prob.dim, r->prob.nbins, r->it < r->prob.ita, prec == 1);
+            const int kern = kernel_of(*r);
+            const size_t lds = lds_bytes_of(r->prob.dim, r->prob.nbins, r->it < r->prob.ita, kern >= 2);
             int o = 0;
-            st = occupancy(prec, lds, &o);
+            st = occupancy(kern, kBatchBlock, lds, &o);
             if (st != MC_OK) return st;
-            r->group = 2 * prec + (o < occ_full[prec] ? 1 : 0);
+            r->group = 2 * kern + (o < occ_full[kern] ? 1 : 0);
         }
         std::stable_sort(active.begin(), active.end(),
                          [](const Request *x, const Request *y) { return x->group < y->group; });
@@ -440,7 +445,7 @@ struct mc_server {
                 max_nb = std::max(max_nb, r->prob.nbins);
             }
             const int grp = r->group;
-            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, grp >= 2));
+            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, grp >= 4));
             first[grp + 1] = i + 1;
         }
         for (int grp = 1; grp <= kGroups; ++grp) first[grp] = std::max(first[grp], first[grp - 1]);
@@ -448,13 +453,23 @@ struct mc_server {
         // segments go to the queue largest first
         std::vector<BatchSegment> segs;
         std::vector<int32_t> item_first(n, -1), order;
-        int G[kGroups] = {}, seg_lo[kGroups + 1] = {};
+        int G[kGroups] = {}, T[kGroups] = {}, seg_lo[kGroups + 1] = {};
         for (int grp = 0; grp < kGroups; ++grp) {
             seg_lo[grp] = (int)segs.size();
             if (first[grp] == first[grp + 1]) continue;
+            const int kern = grp / 2;
             int per_cu = 0;
-            st = occupancy(grp >= 2 ? 1 : 0, lds[grp], &per_cu);
+            st = occupancy(kern, kBatchBlock, lds[grp], &per_cu);
             if (st != MC_OK) return st;
+            T[grp] = kBatchBlock;
+            if (grp % 2 == 1) {  // LDS-limited: larger workgroups keep more waves per CU
+                int wide = 0;
+                if (occupancy(kern, kBatchMaxBlock, lds[grp], &wide) == MC_OK &&
+                    wide * kBatchMaxBlock > per_cu * kBatchBlock) {
+                    per_cu = wide;
+                    T[grp] = kBatchMaxBlock;
+                }
+            }
             G[grp] = per_cu * cus;
             int64_t cubes = 0;
             for (int i = first[grp]; i < first[grp + 1]; ++i) cubes += active[i]->m;
@@ -513,7 +528,7 @@ struct mc_server {
             A.queue = reinterpret_cast<uint32_t *>(step_base + L.queue) + grp;
             A.lo = seg_lo[grp];
             A.hi = seg_lo[grp + 1];
-            HIP_TRY(launch_batch(grp >= 2, G[grp], kBatchBlock, lds[grp], stream, A));
+            HIP_TRY(launch_batch(grp >= 4, grp / 2 % 2 == 1, G[grp], T[grp], lds[grp], stream, A));
         }
         HIP_TRY(hipEventRecord(ev[1], stream));
         HIP_TRY(launch_batch_finalize(A, stream));

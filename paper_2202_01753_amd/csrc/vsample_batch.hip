@@ -64,10 +64,13 @@ __device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegm
     MC_CASE(F, 1) MC_CASE(F, 2) MC_CASE(F, 3) MC_CASE(F, 4) MC_CASE(F, 5) MC_CASE(F, 6)           \
     MC_CASE(F, 7) MC_CASE(F, 8) MC_CASE(F, 9) MC_CASE(F, 10)
 
-// Register budget: every (integrand, dimension) case shares the kernel's
-// allocation, so the largest case sets it.
-template <bool F32>
-__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3)))
+// Register budget: every (integrand, dimension) case of a kernel shares its
+// allocation, so the largest case sets it.  The closed-form integrands fit in
+// 128 VGPRs (4 waves per SIMD); the table integrand in FP64 needs more and
+// gets its own kernel at 3 waves per SIMD, so it does not hold the others back.
+template <bool F32, bool TABLES>
+__global__ void __launch_bounds__(kBatchMaxBlock)
+__attribute__((amdgpu_waves_per_eu(TABLES && !F32 ? 3 : 4)))
 vsample_batch_kernel(const BatchArgs B) {
     extern __shared__ double lds[];
     __shared__ int32_t next;
@@ -75,19 +78,27 @@ vsample_batch_kernel(const BatchArgs B) {
         // every workgroup leaves once the counter has passed hi
         if (threadIdx.x == 0) next = B.lo + (int32_t)atomicAdd(B.queue, 1u);
         __syncthreads();
-        const int32_t q = next;
+        // the same for every lane: keep it (and all that is loaded through
+        // it) in scalar registers
+        const int32_t q = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();
         if (q >= B.hi) break;
         const int si = B.order[q];
         const BatchSegment sg = B.segs[si];
         const SampleArgs &a = B.items[sg.item].a;
-        switch (a.kind) {
-            MC_CASES_1_10(0)
-            MC_CASES_1_10(1)
-            MC_CASES_1_10(2)
-            MC_CASE(3, 4) MC_CASE(3, 5) MC_CASE(3, 6) MC_CASE(3, 7) MC_CASE(3, 8) MC_CASE(3, 9)
-            MC_CASE(3, 10)
-            default: break;
+        if constexpr (TABLES) {
+            switch (a.kind) {
+                MC_CASE(3, 4) MC_CASE(3, 5) MC_CASE(3, 6) MC_CASE(3, 7) MC_CASE(3, 8) MC_CASE(3, 9)
+                MC_CASE(3, 10)
+                default: break;
+            }
+        } else {
+            switch (a.kind) {
+                MC_CASES_1_10(0)
+                MC_CASES_1_10(1)
+                MC_CASES_1_10(2)
+                default: break;
+            }
         }
     }
 }
@@ -223,20 +234,29 @@ hipError_t launch_admit(const AdmitRecord *recs, int n, const char *upload, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_batch(bool fp32, int blocks, int threads, size_t lds_bytes, hipStream_t stream,
-                        const BatchArgs &args) {
+const void *batch_kernel(bool fp32, bool tables) {
     if (fp32)
-        hipLaunchKernelGGL(vsample_batch_kernel<true>, dim3(blocks), dim3(threads), lds_bytes,
-                           stream, args);
-    else
-        hipLaunchKernelGGL(vsample_batch_kernel<false>, dim3(blocks), dim3(threads), lds_bytes,
-                           stream, args);
-    return hipGetLastError();
+        return tables ? reinterpret_cast<const void *>(&vsample_batch_kernel<true, true>)
+                      : reinterpret_cast<const void *>(&vsample_batch_kernel<true, false>);
+    return tables ? reinterpret_cast<const void *>(&vsample_batch_kernel<false, true>)
+                  : reinterpret_cast<const void *>(&vsample_batch_kernel<false, false>);
 }
 
-const void *batch_kernel(bool fp32) {
-    return fp32 ? reinterpret_cast<const void *>(&vsample_batch_kernel<true>)
-                : reinterpret_cast<const void *>(&vsample_batch_kernel<false>);
+hipError_t launch_batch(bool fp32, bool tables, int blocks, int threads, size_t lds_bytes,
+                        hipStream_t stream, const BatchArgs &args) {
+    const dim3 grid(blocks), block(threads);
+    if (fp32) {
+        if (tables)
+            hipLaunchKernelGGL((vsample_batch_kernel<true, true>), grid, block, lds_bytes, stream, args);
+        else
+            hipLaunchKernelGGL((vsample_batch_kernel<true, false>), grid, block, lds_bytes, stream, args);
+    } else {
+        if (tables)
+            hipLaunchKernelGGL((vsample_batch_kernel<false, true>), grid, block, lds_bytes, stream, args);
+        else
+            hipLaunchKernelGGL((vsample_batch_kernel<false, false>), grid, block, lds_bytes, stream, args);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream) {
