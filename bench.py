@@ -45,21 +45,26 @@ PHILOX_BLOCK_OPS = 17 + 18
 
 
 def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float:
-    """Algorithmic VALU lane-operations per sample of the FP64 path.
+    """Algorithmic VALU lane-operations per sample of the FP64 path (or of the
+    FP32-evaluation path with fp32 set).
 
     Counted from the method's steps at one issue slot per full-rate VALU
     instruction (measured on gfx950: 32x32->64 integer products, FP64 add/mul/
-    fma and conversions all issue at the full rate; v_rcp_f64 counts 4; a
-    three-input XOR is one v_bitop3_b32), with work that is uniform across the
-    wavefront or invariant across a sub-cube's samples excluded:
-      Philox4x32-10 block       17 products + 18 three-way XOR (ceil(d/2) blocks)
-      per axis                  uniform 5, stratified coordinate 2, bin index
-                                and clamp 7, boundary address and width 2,
-                                point 2, Jacobian 2           = 20
-      Gaussian product          3 per axis + exp 20
-      corner peak               d fma + binary powering + division 13
-      two bilinear tables       2 x 21 + 2 products (on top of the Gaussian)
-      f J / (m p), finiteness   4
+    fma and conversions all issue at the full rate; v_rcp_f64, v_rcp_f32 count
+    4 and v_exp_f32 2; a three-input XOR is one v_bitop3_b32), with work that
+    is uniform across the wavefront or invariant across a sub-cube's samples
+    excluded:
+                                FP64 path                      FP32 evaluation
+      Philox4x32-10 block       17 products + 18 three-way XOR, ceil(d/2) blocks; ceil(d/4)
+      per axis                  20: uniform 5, coordinate 2,   15: uniform 3, coordinate 2,
+                                bin index and clamp 7, address bin index and clamp 5, address
+                                and width 2, point 2,          1, point 2, Jacobian 2
+                                Jacobian 2
+      Gaussian product          3 per axis + exp 20            3 per axis + expf 10
+      corner peak               d fma + binary powering +      d fma + powering +
+                                division 13                    division 12
+      two bilinear tables       2 x 21 + 2 products (on top of the Gaussian), both paths
+      f J / (m p), finiteness   4                              6 (two widening conversions)
       shifted sums              3 (p-1)/p
       bin contributions         1 + d addresses (adjusting iterations)
       per sub-cube, / p         variance 5, two compensated additions 14,
@@ -68,20 +73,19 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float
     d = int(prob["dim"])
     _, _, p = g_m_p
     kind = prob["integrand"]
-    philox = math.ceil(d / 2) * PHILOX_BLOCK_OPS
-    per_axis = 20 * d
+    philox = math.ceil(d / (4 if fp32 else 2)) * PHILOX_BLOCK_OPS
+    per_axis = (15 if fp32 else 20) * d
+    expo, div = (10, 12) if fp32 else (20, 13)
     if kind == "const":
         f = 0
     elif kind == "gauss_product":
-        f = 3 * d + 20
+        f = 3 * d + expo
     elif kind == "corner_peak":
         e = d + 1
-        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + 13
+        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + div
     else:
-        f = 3 * d + 20 + 2 * 21 + 2
-    tail = 4 + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (19 + 5 * d) / p
-    if fp32:  # FP32-eval needs only the first ceil(d/4) blocks; the rest is counted alike
-        philox = math.ceil(d / 4) * PHILOX_BLOCK_OPS
+        f = 3 * d + expo + 2 * 21 + 2
+    tail = (6 if fp32 else 4) + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (19 + 5 * d) / p
     return float(philox + per_axis + f + tail)
 
 

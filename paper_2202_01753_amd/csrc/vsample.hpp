@@ -234,10 +234,20 @@ __device__ __forceinline__ void load_lds(const SampleArgs &a, const LdsView<F32>
         for (int i = tid; i < D * nb; i += nthr) v.hist[i] = 0.0;
 }
 
+// Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
+// independent evaluations interleave and hide each other's LDS and
+// transcendental latency, but both must fit in registers: measured on gfx950
+// this pays for FP32 evaluation up to d = 11 and for the FP64 table integrand
+// up to d = 6, and costs elsewhere in FP64, where the pair spills.
+template <int F, int D, bool F32>
+constexpr bool kPairSamples = F32 ? D <= 11 : (F == 3 && D <= 6);
+
 // All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
 // contributions to the LDS histogram when collecting them, and records the
-// cube in the trace when tracing.
-template <int F, int D, bool TRACE, bool F32>
+// cube in the trace when tracing.  PAIR: evaluate the samples two at a time
+// (kPairSamples for a kernel of its own; kernels that inline many cases into
+// one register allocation leave it off).
+template <int F, int D, bool TRACE, bool F32, bool PAIR>
 __device__ __forceinline__ void cube_pass(const SampleArgs &a, const LdsView<F32> &v, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad) {
@@ -259,77 +269,181 @@ __device__ __forceinline__ void cube_pass(const SampleArgs &a, const LdsView<F32
     const bool traced = TRACE && (int64_t)t >= a.t0 && (int64_t)t < a.t1;
 
     double I0 = 0.0, S1 = 0.0, S2 = 0.0;
-    for (int k = 0; k < a.p; ++k) {
-        uint32_t w[4 * NUSED];
+    if constexpr (PAIR) {
+        // One sample: its value I_k and its bin on every axis (and its trace record).
+        auto point = [&](int k, int (&bin)[D]) -> double {
+            uint32_t w[4 * NUSED];
 #pragma unroll
-        for (int b = 0; b < NUSED; ++b) {
-            uint32_t x0 = (uint32_t)(k * NBLK + b), x1 = a.iter, x2 = tlo, x3 = thi;
-            philox4x32_10(x0, x1, x2, x3, k0, k1);
-            w[4 * b] = x0;
-            w[4 * b + 1] = x1;
-            w[4 * b + 2] = x2;
-            w[4 * b + 3] = x3;
-        }
-        Integrand<F, D, R> fx;
-        int bin[D];
-        R J = R(1);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            R u;
-            if constexpr (F32) u = uniform24(w[j]);
-            else u = uniform53(w[j], w[D + j]);
-            const R z = (cd[j] + u) * s;
-            // bin index, clamped to the last bin with fraction 1 there: once
-            // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
-            // gives exactly 1; otherwise z - floor(z) < 1 is exact.
-            const R fz = rmin(rfloor(z), last);
-            const int i = (int)fz;
-            const R frac = rmin(z - fz, R(1));
-            R left, width;
-            if constexpr (F32) {
-                const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
-                left = cell.x;
-                width = cell.y;
-            } else {
-                const R *B = sG + j * row + i;
-                left = B[0];
-                width = B[1] - left;
+            for (int b = 0; b < NUSED; ++b) {
+                uint32_t x0 = (uint32_t)(k * NBLK + b), x1 = a.iter, x2 = tlo, x3 = thi;
+                philox4x32_10(x0, x1, x2, x3, k0, k1);
+                w[4 * b] = x0;
+                w[4 * b + 1] = x1;
+                w[4 * b + 2] = x2;
+                w[4 * b + 3] = x3;
             }
-            const R xu = rfma(frac, width, left);
-            const R *cj = sC + kConstStride * j;
-            const R xj = rfma(cj[1], xu, cj[0]);
-            J = J * (width * cj[2]);
-            bin[j] = i;
-            fx.axis(j, xj, cj);
+            Integrand<F, D, R> fx;
+            R J = R(1);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                R u;
+                if constexpr (F32) u = uniform24(w[j]);
+                else u = uniform53(w[j], w[D + j]);
+                const R z = (cd[j] + u) * s;
+                // bin index, clamped to the last bin with fraction 1 there: once
+                // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
+                // gives exactly 1; otherwise z - floor(z) < 1 is exact.
+                const R fz = rmin(rfloor(z), last);
+                const int i = (int)fz;
+                const R frac = rmin(z - fz, R(1));
+                R left, width;
+                if constexpr (F32) {
+                    const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
+                    left = cell.x;
+                    width = cell.y;
+                } else {
+                    const R *B = sG + j * row + i;
+                    left = B[0];
+                    width = B[1] - left;
+                }
+                const R xu = rfma(frac, width, left);
+                const R *cj = sC + kConstStride * j;
+                const R xj = rfma(cj[1], xu, cj[0]);
+                J = J * (width * cj[2]);
+                bin[j] = i;
+                fx.axis(j, xj, cj);
+                if (traced) {
+                    double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
+                    r[j] = (double)u;
+                    r[D + j] = (double)i;
+                    r[2 * D + j] = (double)xj;
+                }
+            }
+            const R f = fx.value(a);
+            bad |= !isfinite(f);
             if (traced) {
                 double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
-                r[j] = (double)u;
-                r[D + j] = (double)i;
-                r[2 * D + j] = (double)xj;
+                r[3 * D] = (double)J;
+                r[3 * D + 1] = (double)f;
+            }
+            const double Fv = (double)f * (double)J;
+            return Fv * a.inv;
+        };
+        // shifted sums in sample order
+        auto accumulate = [&](int k, double Ik) {
+            if (k == 0) {
+                I0 = Ik;
+            } else {
+                const double dev = Ik - I0;
+                S1 = S1 + dev;
+                S2 = __fma_rn(dev, dev, S2);
+            }
+        };
+        auto add_bins = [&](const int (&bin)[D], double Ik) {
+            if (a.hist) {
+                const double sq = Ik * Ik;
+                const int axes = a.one_d ? 1 : D;
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (j < axes) atomicAdd(&sH[j * nb + bin[j]], sq);
+            }
+        };
+        {
+            // both points (grid reads included) before either sample's histogram
+            // atomics, so that the two evaluations can interleave
+            int k = 0;
+            for (; k + 1 < a.p; k += 2) {
+                int bin0[D], bin1[D];
+                const double Ia = point(k, bin0);
+                const double Ib = point(k + 1, bin1);
+                accumulate(k, Ia);
+                accumulate(k + 1, Ib);
+                add_bins(bin0, Ia);
+                add_bins(bin1, Ib);
+            }
+            if (k < a.p) {
+                int bin0[D];
+                const double Ia = point(k, bin0);
+                accumulate(k, Ia);
+                add_bins(bin0, Ia);
             }
         }
-        const R f = fx.value(a);
-        bad |= !isfinite(f);
-        const double Fv = (double)f * (double)J;
-        const double Ik = Fv * a.inv;
-        if (k == 0) {
-            I0 = Ik;
-        } else {
-            const double dev = Ik - I0;
-            S1 = S1 + dev;
-            S2 = __fma_rn(dev, dev, S2);
-        }
-        if (a.hist) {
-            const double sq = Ik * Ik;
-            const int axes = a.one_d ? 1 : D;
+    } else {
+        // the same steps one sample at a time, written out in the loop: the
+        // batched kernel, which inlines every case, allocates fewer registers
+        // for this form than for the lambda one
+        for (int k = 0; k < a.p; ++k) {
+            uint32_t w[4 * NUSED];
 #pragma unroll
-            for (int j = 0; j < D; ++j)
-                if (j < axes) atomicAdd(&sH[j * nb + bin[j]], sq);
-        }
-        if (traced) {
-            double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
-            r[3 * D] = (double)J;
-            r[3 * D + 1] = (double)f;
+            for (int b = 0; b < NUSED; ++b) {
+                uint32_t x0 = (uint32_t)(k * NBLK + b), x1 = a.iter, x2 = tlo, x3 = thi;
+                philox4x32_10(x0, x1, x2, x3, k0, k1);
+                w[4 * b] = x0;
+                w[4 * b + 1] = x1;
+                w[4 * b + 2] = x2;
+                w[4 * b + 3] = x3;
+            }
+            Integrand<F, D, R> fx;
+            int bin[D];
+            R J = R(1);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                R u;
+                if constexpr (F32) u = uniform24(w[j]);
+                else u = uniform53(w[j], w[D + j]);
+                const R z = (cd[j] + u) * s;
+                // bin index, clamped to the last bin with fraction 1 there: once
+                // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
+                // gives exactly 1; otherwise z - floor(z) < 1 is exact.
+                const R fz = rmin(rfloor(z), last);
+                const int i = (int)fz;
+                const R frac = rmin(z - fz, R(1));
+                R left, width;
+                if constexpr (F32) {
+                    const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
+                    left = cell.x;
+                    width = cell.y;
+                } else {
+                    const R *B = sG + j * row + i;
+                    left = B[0];
+                    width = B[1] - left;
+                }
+                const R xu = rfma(frac, width, left);
+                const R *cj = sC + kConstStride * j;
+                const R xj = rfma(cj[1], xu, cj[0]);
+                J = J * (width * cj[2]);
+                bin[j] = i;
+                fx.axis(j, xj, cj);
+                if (traced) {
+                    double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
+                    r[j] = (double)u;
+                    r[D + j] = (double)i;
+                    r[2 * D + j] = (double)xj;
+                }
+            }
+            const R f = fx.value(a);
+            bad |= !isfinite(f);
+            const double Fv = (double)f * (double)J;
+            const double Ik = Fv * a.inv;
+            if (k == 0) {
+                I0 = Ik;
+            } else {
+                const double dev = Ik - I0;
+                S1 = S1 + dev;
+                S2 = __fma_rn(dev, dev, S2);
+            }
+            if (a.hist) {
+                const double sq = Ik * Ik;
+                const int axes = a.one_d ? 1 : D;
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (j < axes) atomicAdd(&sH[j * nb + bin[j]], sq);
+            }
+            if (traced) {
+                double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
+                r[3 * D] = (double)J;
+                r[3 * D + 1] = (double)f;
+            }
         }
     }
     It = __fma_rn(a.pd, I0, S1);
@@ -427,7 +541,7 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     bool bad = false;
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32>(a, v, t, dig, It, vt, bad);
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>>(a, v, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         // next sub-cube of this lane: t += stride, digit by digit

@@ -38,7 +38,7 @@ __device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegm
     bool bad = false;
     while (t < (uint64_t)sg.t1) {
         double It, vt;
-        cube_pass<F, D, false, F32>(a, v, t, dig, It, vt, bad);
+        cube_pass<F, D, false, F32, false>(a, v, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         t += blockDim.x;
