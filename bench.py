@@ -214,6 +214,7 @@ def bench_batch(args, M, W, torch):
                         "avg_launch_ms": sample_s / sum(s.steps for s in stats) * 1e3}
     line["kernel_samples_per_s"] = calls / sample_s
     line["steps_per_batch"] = stats[0].steps
+    line["host_ms_per_batch"] = sum(s.host_ms for s in stats) / len(stats)
     print(json.dumps(line))
 
 
@@ -265,7 +266,8 @@ def bench_serve(args, M, W, torch):
     line["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                           "mean": float(lat.mean()), "max": float(lat.max())}
     line["served"] = {"failed": fails, "server_steps": st.steps, "max_active": st.max_active,
-                      "sampling_ms": st.sample_ms, "wall_ms": el * 1e3}
+                      "sampling_ms": st.sample_ms, "server_host_ms": st.host_ms,
+                      "server_step_ms": st.step_ms, "wall_ms": el * 1e3}
     print(json.dumps(line))
 
 

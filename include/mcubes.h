@@ -218,6 +218,8 @@ typedef struct mc_batch_stats {
     double sample_ms;    /* sampling-launch time summed over steps (HIP events) */
     double step_ms;      /* host wall time of the steps */
     int64_t calls;       /* integrand evaluations over all integrals */
+    double host_ms;      /* host work of the steps: admission and step set-up before the
+                            launches, and the per-integral host steps after the read-back */
 } mc_batch_stats;
 
 /* Device workspace for running the n problems together with
@@ -239,7 +241,9 @@ mc_status mc_batch_integrate(const mc_problem *probs, int32_t n, void *d_ws, siz
  * state (constants, tables, two grids and the latest histogram per
  * integral); the rest holds one step's work tables.  Requests are admitted
  * in arrival order when both fit, at most max_active at a time.  One server
- * must not be used from two threads at once. */
+ * must not be used from two threads at once.  Device memory is only the
+ * caller's workspace; the server keeps its host copies of the requests and a
+ * page-locked host buffer for each step's upload and read-back. */
 typedef struct mc_server mc_server;
 
 mc_status mc_server_create(void *d_ws, size_t ws_bytes, size_t arena_bytes, int32_t max_active,

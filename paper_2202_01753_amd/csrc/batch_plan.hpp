@@ -1,0 +1,126 @@
+// Host-side planning of a batched step, free of any device call, so that the
+// CPU test suite can compile and check it on its own:
+//   * Arena: first-fit allocation of the integrals' persistent blocks in the
+//     device workspace (offsets only), with coalescing of free neighbours;
+//   * split_work: cutting a group of integrals' sub-cubes into segments of
+//     bounded work;
+//   * largest_first: the order in which a launch's workgroups take them.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <iterator>
+#include <map>
+#include <numeric>
+#include <vector>
+
+namespace mcubes {
+namespace plan {
+
+constexpr size_t kArenaAlign = 256;
+
+inline size_t arena_round(size_t v) { return (v + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+// First-fit allocator over [0, cap) in kArenaAlign units; freed ranges merge
+// with free neighbours.
+class Arena {
+  public:
+    explicit Arena(size_t cap) {
+        cap = cap / kArenaAlign * kArenaAlign;
+        if (cap) free_[0] = cap;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = arena_round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, next = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[next] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = arena_round(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (const auto &kv : free_) s += kv.second;
+        return s;
+    }
+    size_t free_ranges() const { return free_.size(); }
+
+  private:
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+// A contiguous range [t0, t1) of integral `item`'s sub-cubes.
+struct Piece {
+    int32_t item;
+    int64_t t0, t1;
+};
+
+// Cuts the work of integrals first..last-1 (m[i] sub-cubes of cost[i] each)
+// into `parts` equal shares laid end to end, and every integral into the
+// pieces the cuts leave (an integral smaller than a share stays whole).
+// Appends the pieces in integral order, each integral's in sub-cube order;
+// first_piece[i] is set to the index of integral i's first piece.  At most
+// (last - first) + parts + 1 pieces are appended.
+inline void split_work(const int64_t *m, const double *cost, int first, int last, int64_t parts,
+                       std::vector<Piece> &out, int32_t *first_piece) {
+    double W = 0.0;
+    std::vector<double> start(last - first + 1);
+    for (int i = first; i < last; ++i) {
+        start[i - first] = W;
+        W += (double)m[i] * cost[i];
+    }
+    start[last - first] = W;
+    const double share = W / (double)std::max<int64_t>(parts, 1);
+    for (int i = first; i < last; ++i) {
+        first_piece[i] = (int32_t)out.size();
+        const double a = start[i - first], b = start[i + 1 - first];
+        int64_t t0 = 0;
+        if (share > 0.0) {
+            for (double x = std::ceil(a / share) * share; x < b; x += share) {
+                const int64_t t = std::min<int64_t>((int64_t)std::llround((x - a) / cost[i]), m[i]);
+                if (t <= t0) continue;
+                out.push_back(Piece{i, t0, t});
+                t0 = t;
+            }
+        }
+        if (t0 < m[i]) out.push_back(Piece{i, t0, m[i]});
+    }
+}
+
+// Indices lo..hi-1 of `pieces`, largest work first (ties in index order),
+// appended to order.
+inline void largest_first(const std::vector<Piece> &pieces, const double *cost, int lo, int hi,
+                          std::vector<int32_t> &order) {
+    std::vector<double> work(hi - lo);
+    for (int k = lo; k < hi; ++k)
+        work[k - lo] = (double)(pieces[k].t1 - pieces[k].t0) * cost[pieces[k].item];
+    const size_t o0 = order.size();
+    order.resize(o0 + (hi - lo));
+    std::iota(order.begin() + o0, order.end(), lo);
+    std::stable_sort(order.begin() + o0, order.end(),
+                     [&](int32_t x, int32_t y) { return work[x - lo] > work[y - lo]; });
+}
+
+}  // namespace plan
+}  // namespace mcubes

@@ -22,65 +22,60 @@
 //   4. reads back 4 doubles per integral and runs Weighted-Estimates and
 //      Check-Convergence on the host; finished integrals release their block.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
 #include <unordered_map>
 
+#include "batch_plan.hpp"
 #include "host.hpp"
 #include "internal.hpp"
 #include "mcubes.h"
 
 using namespace mcubes;
 using namespace mcubes::host;
+using mcubes::plan::Arena;
 
 namespace {
 
-// First-fit allocator over [0, cap) with coalescing of neighbours.
-class Arena {
+// Page-locked host memory (hipHostMalloc), grown on demand, so that a step's
+// upload and read-back are asynchronous copies.  Only resized between steps,
+// when no copy from or to it is in flight.
+class Pinned {
   public:
-    explicit Arena(size_t cap) {
-        if (cap) free_[0] = cap;
+    Pinned() = default;
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
+    ~Pinned() {
+        if (p_) (void)hipHostFree(p_);
     }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = align_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes, next = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[next] = rest;
-            return true;
+    hipError_t reserve(size_t bytes) {
+        if (bytes <= cap_) return hipSuccess;
+        const size_t prev = cap_;
+        if (p_) {
+            const hipError_t e = hipHostFree(p_);
+            p_ = nullptr;
+            cap_ = 0;
+            if (e != hipSuccess) return e;
         }
-        return false;
+        const size_t want = std::max({bytes, 2 * prev, size_t(1) << 20});  // geometric growth
+        const hipError_t e = hipHostMalloc(&p_, want, hipHostMallocDefault);
+        if (e == hipSuccess) cap_ = want;
+        return e;
     }
-    void release(size_t off, size_t bytes) {
-        bytes = align_up(bytes);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+    char *data() const { return static_cast<char *>(p_); }
 
   private:
-    std::map<size_t, size_t> free_;
+    void *p_ = nullptr;
+    size_t cap_ = 0;
 };
 
 struct Request {
     int64_t id = 0;
     mc_problem prob{};
     std::vector<double> params, tables, lo, hi;
-    std::vector<float> tables32;   // FP32-eval tables, kept until the request is released
     std::vector<char> consts_img;  // per-axis constants in the device precision, until admitted
     int64_t g = 0, m = 0, p = 0;
     int32_t state = MC_REQ_QUEUED;
@@ -230,8 +225,9 @@ struct mc_server {
     std::map<std::pair<size_t, int>, int> occ_cache[kKernels];  // workgroups per CU by (LDS, threads)
     int occ_full[kKernels] = {};  // the register-limited occupancy (256-thread workgroups)
     StepNeed need;  // of the active set
-    std::vector<char> staging;
-    std::vector<double> res;
+    Pinned staging;    // the step's upload
+    Pinned tab_stage;  // tables of the integrals admitted in this step
+    Pinned res_buf;  // the step's read-back: 4 doubles per integral
     hipEvent_t ev[2] = {nullptr, nullptr};
     mc_batch_stats stats{};
 
@@ -316,6 +312,7 @@ struct mc_server {
     // Admits queued integrals in arrival order while their blocks and the
     // step area fit.
     mc_status admit() {
+        const size_t first_new = admitted.size();
         while (!queue.empty() && (int32_t)active.size() < max_active) {
             Request *r = queue.front();
             StepNeed grown = need;
@@ -331,26 +328,16 @@ struct mc_server {
             r->off_grid[0] = off + og0;
             r->off_grid[1] = off + og1;
             r->off_out = off + oo;
-            // tables now, from host memory the request keeps; constants and the
-            // starting grid with the step's upload (admit_kernel)
+            // constants and the starting grid travel with the step's upload
+            // (admit_kernel); the tables are copied below
             const std::vector<double> c = axis_constants(&r->prob);
             if (fp32_of(*r)) {
                 const std::vector<float> c32(c.begin(), c.end());
                 r->consts_img.assign(reinterpret_cast<const char *>(c32.data()),
                                      reinterpret_cast<const char *>(c32.data() + c32.size()));
-                if (!r->tables.empty()) {
-                    r->tables32.assign(r->tables.begin(), r->tables.end());
-                    HIP_TRY(hipMemcpyAsync(ws + r->off_tables, r->tables32.data(),
-                                           sizeof(float) * r->tables32.size(), hipMemcpyHostToDevice,
-                                           stream));
-                }
             } else {
                 r->consts_img.assign(reinterpret_cast<const char *>(c.data()),
                                      reinterpret_cast<const char *>(c.data() + c.size()));
-                if (!r->tables.empty())
-                    HIP_TRY(hipMemcpyAsync(ws + r->off_tables, r->tables.data(),
-                                           sizeof(double) * r->tables.size(), hipMemcpyHostToDevice,
-                                           stream));
             }
             admitted.push_back(r);
             r->cur = 0;
@@ -359,46 +346,43 @@ struct mc_server {
             active.push_back(r);
             need = grown;
         }
-        return MC_OK;
-    }
-
-    // Splits the items [first, last) of one launch group into segments: the
-    // group's work is cut into `parts` equal shares and every item into the
-    // pieces the cuts leave (items smaller than a share stay whole).
-    // Appends to segs; item_first[i] is set to the item's first segment.
-    void split(const std::vector<Request *> &items, int first, int last, int64_t parts,
-               std::vector<BatchSegment> &segs, std::vector<int32_t> &item_first) {
-        double W = 0.0;
-        std::vector<double> start(last - first + 1);
-        for (int i = first; i < last; ++i) {
-            start[i - first] = W;
-            W += (double)items[i]->m * items[i]->cost;
-        }
-        start[last - first] = W;
-        const double share = W / (double)parts;
-        for (int i = first; i < last; ++i) {
-            const Request &r = *items[i];
-            item_first[i] = (int32_t)segs.size();
-            // cuts at multiples of share inside the item, in sub-cube units
-            const double a = start[i - first], b = start[i + 1 - first];
-            int64_t t0 = 0;
-            for (double x = std::ceil(a / share) * share; x < b; x += share) {
-                const int64_t t = std::min<int64_t>((int64_t)std::llround((x - a) / r.cost), r.m);
-                if (t <= t0) continue;
-                segs.push_back(BatchSegment{i, 0, t0, t});
-                t0 = t;
+        // the new integrals' tables (in their device precision), packed into
+        // page-locked memory and copied from there
+        size_t tab_bytes = 0;
+        for (size_t k = first_new; k < admitted.size(); ++k)
+            if (!admitted[k]->tables.empty())
+                tab_bytes += align_up((fp32_of(*admitted[k]) ? sizeof(float) : sizeof(double)) * kTablesLen);
+        if (tab_bytes) {
+            HIP_TRY(hipStreamSynchronize(stream));  // no copy from tab_stage is in flight
+            HIP_TRY(tab_stage.reserve(tab_bytes));
+            size_t off = 0;
+            for (size_t k = first_new; k < admitted.size(); ++k) {
+                const Request *r = admitted[k];
+                if (r->tables.empty()) continue;
+                char *dst = tab_stage.data() + off;
+                size_t bytes;
+                if (fp32_of(*r)) {
+                    float *f = reinterpret_cast<float *>(dst);
+                    for (size_t i = 0; i < kTablesLen; ++i) f[i] = (float)r->tables[i];
+                    bytes = sizeof(float) * kTablesLen;
+                } else {
+                    std::memcpy(dst, r->tables.data(), sizeof(double) * kTablesLen);
+                    bytes = sizeof(double) * kTablesLen;
+                }
+                HIP_TRY(hipMemcpyAsync(ws + r->off_tables, dst, bytes, hipMemcpyHostToDevice, stream));
+                off += align_up(bytes);
             }
-            if (t0 < r.m) segs.push_back(BatchSegment{i, 0, t0, r.m});
         }
+        return MC_OK;
     }
 
     mc_status step(int32_t *n_finished) {
         *n_finished = 0;
         last_finished.clear();
+        const auto t_start = std::chrono::steady_clock::now();
         mc_status st = admit();
         if (st != MC_OK) return st;
         if (active.empty()) return MC_OK;
-        const auto t_start = std::chrono::steady_clock::now();
         // launch groups: the kernel, then whether the integral's LDS footprint
         // still allows the kernel's register-limited workgroups per CU
         for (Request *r : active) {
@@ -415,7 +399,8 @@ struct mc_server {
 
         char *step_base = ws + arena_bytes;
         const StepLayout L = step_layout(need, gcap);
-        staging.assign(L.upload_end, 0);
+        HIP_TRY(staging.reserve(L.upload_end));
+        std::memset(staging.data(), 0, L.upload_end);
         BatchItem *items = reinterpret_cast<BatchItem *>(staging.data() + L.items);
         int32_t *item_first_h = reinterpret_cast<int32_t *>(staging.data() + L.item_first);
         double **next_grid = reinterpret_cast<double **>(staging.data() + L.next_grid);
@@ -451,8 +436,14 @@ struct mc_server {
         for (int grp = 1; grp <= kGroups; ++grp) first[grp] = std::max(first[grp], first[grp - 1]);
         // work split per group, each group one launch filling the GPU; its
         // segments go to the queue largest first
-        std::vector<BatchSegment> segs;
+        std::vector<plan::Piece> segs;
         std::vector<int32_t> item_first(n, -1), order;
+        std::vector<int64_t> cubes_of(n);
+        std::vector<double> costs(n);
+        for (int i = 0; i < n; ++i) {
+            cubes_of[i] = active[i]->m;
+            costs[i] = active[i]->cost;
+        }
         int G[kGroups] = {}, T[kGroups] = {}, seg_lo[kGroups + 1] = {};
         for (int grp = 0; grp < kGroups; ++grp) {
             seg_lo[grp] = (int)segs.size();
@@ -475,20 +466,17 @@ struct mc_server {
             for (int i = first[grp]; i < first[grp + 1]; ++i) cubes += active[i]->m;
             const int64_t parts =
                 std::max<int64_t>(1, std::min<int64_t>((int64_t)kSegsPerWg * G[grp], cubes / kMinSegCubes));
-            split(active, first[grp], first[grp + 1], parts, segs, item_first);
-            const size_t o0 = order.size();
-            for (int k = seg_lo[grp]; k < (int)segs.size(); ++k) order.push_back(k);
-            auto work = [&](int32_t k) {
-                return (double)(segs[k].t1 - segs[k].t0) * active[segs[k].item]->cost;
-            };
-            std::stable_sort(order.begin() + o0, order.end(),
-                             [&](int32_t x, int32_t y) { return work(x) > work(y); });
+            plan::split_work(cubes_of.data(), costs.data(), first[grp], first[grp + 1], parts, segs,
+                             item_first.data());
+            plan::largest_first(segs, costs.data(), seg_lo[grp], (int)segs.size(), order);
         }
         seg_lo[kGroups] = (int)segs.size();
         if ((int64_t)segs.size() > L.nseg) return MC_EINVAL;  // cannot happen: the layout's bound
         for (int i = 0; i < n; ++i) item_first_h[i] = item_first[i];
         item_first_h[n] = (int32_t)segs.size();
-        std::memcpy(staging.data() + L.segs, segs.data(), sizeof(BatchSegment) * segs.size());
+        BatchSegment *segs_h = reinterpret_cast<BatchSegment *>(staging.data() + L.segs);
+        for (size_t k = 0; k < segs.size(); ++k)
+            segs_h[k] = BatchSegment{segs[k].item, 0, segs[k].t0, segs[k].t1};
         std::memcpy(staging.data() + L.order, order.data(), sizeof(int32_t) * order.size());
         // the queue counters are zero: the staging buffer is cleared every step
         // admissions of this step: constants into the upload, records for admit_kernel
@@ -536,9 +524,13 @@ struct mc_server {
         HIP_TRY(launch_batch_refine(A.items, reinterpret_cast<const int32_t *>(step_base + L.axis_item),
                                     reinterpret_cast<double *const *>(step_base + L.next_grid), n_axes,
                                     max_nb, stream));
-        res.resize(4 * (size_t)n);
-        HIP_TRY(hipMemcpyAsync(res.data(), A.res, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(res_buf.reserve(sizeof(double) * 4 * (size_t)n));
+        const double *res = reinterpret_cast<const double *>(res_buf.data());
+        HIP_TRY(hipMemcpyAsync(res_buf.data(), A.res, sizeof(double) * 4 * n, hipMemcpyDeviceToHost,
+                               stream));
+        const auto t_launched = std::chrono::steady_clock::now();
         HIP_TRY(hipStreamSynchronize(stream));
+        const auto t_synced = std::chrono::steady_clock::now();
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
 
@@ -575,7 +567,9 @@ struct mc_server {
         stats.steps += 1;
         stats.max_active = std::max<int32_t>(stats.max_active, n);
         stats.sample_ms += ms;
-        stats.step_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        const auto t_end = std::chrono::steady_clock::now();
+        stats.step_ms += std::chrono::duration<double, std::milli>(t_end - t_start).count();
+        stats.host_ms += std::chrono::duration<double, std::milli>((t_launched - t_start) + (t_end - t_synced)).count();
         return MC_OK;
     }
 };

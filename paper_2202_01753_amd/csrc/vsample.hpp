@@ -133,7 +133,8 @@ struct Integrand {
         }
     }
 
-    __device__ __forceinline__ R value(const SampleArgs &a) const {
+    template <typename A>
+    __device__ __forceinline__ R value(const A &a) const {
         if constexpr (F == 0) {
             return R(a.cval);
         } else if constexpr (F == 1) {
@@ -213,9 +214,10 @@ struct LdsView {
 };
 
 // Copies the integral's constants and grid into LDS and clears the histogram.
-// Callers synchronise the workgroup afterwards.
-template <int D, bool F32>
-__device__ __forceinline__ void load_lds(const SampleArgs &a, const LdsView<F32> &v) {
+// Callers synchronise the workgroup afterwards.  (A is SampleArgs, possibly
+// in the constant address space: see the batched kernel.)
+template <int D, bool F32, typename A>
+__device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
     using R = real_t<F32>;
     const int nb = a.nb, row = nb + 1, tid = threadIdx.x, nthr = blockDim.x;
     const R *gconst = static_cast<const R *>(a.consts);
@@ -247,8 +249,8 @@ constexpr bool kPairSamples = F32 ? D <= 11 : (F == 3 && D <= 6);
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
 // (kPairSamples for a kernel of its own; kernels that inline many cases into
 // one register allocation leave it off).
-template <int F, int D, bool TRACE, bool F32, bool PAIR>
-__device__ __forceinline__ void cube_pass(const SampleArgs &a, const LdsView<F32> &v, uint64_t t,
+template <int F, int D, bool TRACE, bool F32, bool PAIR, typename A>
+__device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad) {
     using R = real_t<F32>;

@@ -17,8 +17,15 @@ namespace mcubes {
 
 namespace {
 
+// The step's tables (items, segments, queue order) are written by the host
+// before the launch and only read during it, so they are read through the
+// constant address space: uniform loads become scalar loads that the
+// compiler may repeat instead of holding every argument in registers.
+template <typename T>
+using Const = __attribute__((address_space(4))) const T;
+
 template <int F, int D, bool F32>
-__device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegment &sg, int si,
+__device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSegment &sg, int si,
                                             double *lds, const BatchArgs &B) {
     const LdsView<F32> v(lds, D, a.nb);
     load_lds<D, F32>(a, v);
@@ -65,12 +72,12 @@ __device__ __forceinline__ void run_segment(const SampleArgs &a, const BatchSegm
     MC_CASE(F, 7) MC_CASE(F, 8) MC_CASE(F, 9) MC_CASE(F, 10)
 
 // Register budget: every (integrand, dimension) case of a kernel shares its
-// allocation, so the largest case sets it.  The closed-form integrands fit in
-// 128 VGPRs (4 waves per SIMD); the table integrand in FP64 needs more and
-// gets its own kernel at 3 waves per SIMD, so it does not hold the others back.
+// allocation, so the largest case sets it.  With the arguments read through
+// the constant address space every kernel fits 128 VGPRs (4 waves per SIMD);
+// the table integrand, the largest, still has a kernel of its own so that its
+// cases do not set the budget of the others.
 template <bool F32, bool TABLES>
-__global__ void __launch_bounds__(kBatchMaxBlock)
-__attribute__((amdgpu_waves_per_eu(TABLES && !F32 ? 3 : 4)))
+__global__ void __launch_bounds__(kBatchMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 vsample_batch_kernel(const BatchArgs B) {
     extern __shared__ double lds[];
     __shared__ int32_t next;
@@ -83,9 +90,10 @@ vsample_batch_kernel(const BatchArgs B) {
         const int32_t q = __builtin_amdgcn_readfirstlane(next);
         __syncthreads();
         if (q >= B.hi) break;
-        const int si = B.order[q];
-        const BatchSegment sg = B.segs[si];
-        const SampleArgs &a = B.items[sg.item].a;
+        const int si = ((Const<int32_t> *)B.order)[q];
+        Const<BatchSegment> &sgc = ((Const<BatchSegment> *)B.segs)[si];
+        const BatchSegment sg{sgc.item, 0, sgc.t0, sgc.t1};
+        Const<SampleArgs> &a = ((Const<BatchItem> *)B.items)[sg.item].a;
         if constexpr (TABLES) {
             switch (a.kind) {
                 MC_CASE(3, 4) MC_CASE(3, 5) MC_CASE(3, 6) MC_CASE(3, 7) MC_CASE(3, 8) MC_CASE(3, 9)

@@ -68,7 +68,7 @@ class Result(C.Structure):
 
 class BatchStats(C.Structure):
     _fields_ = [("steps", C.c_int32), ("max_active", C.c_int32), ("sample_ms", C.c_double),
-                ("step_ms", C.c_double), ("calls", C.c_int64)]
+                ("step_ms", C.c_double), ("calls", C.c_int64), ("host_ms", C.c_double)]
 
 
 class Timing(C.Structure):
