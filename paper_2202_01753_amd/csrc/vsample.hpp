@@ -238,11 +238,12 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
 
 // Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
 // independent evaluations interleave and hide each other's LDS and
-// transcendental latency, but both must fit in registers: measured on gfx950
-// this pays for FP32 evaluation up to d = 11 and for the FP64 table integrand
-// up to d = 6, and costs elsewhere in FP64, where the pair spills.
+// transcendental latency, but both must fit in registers: in FP32 evaluation
+// they do (up to d = 11, d = 8 with tables) and the pair is 6% faster on the
+// table workload; in FP64 the pair spills to scratch memory (over 1 GB of
+// HBM writes per launch at d = 6), so FP64 keeps one sample at a time.
 template <int F, int D, bool F32>
-constexpr bool kPairSamples = F32 ? D <= 11 : (F == 3 && D <= 6);
+constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 : D <= 11);
 
 // All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
 // contributions to the LDS histogram when collecting them, and records the
