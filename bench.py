@@ -126,6 +126,7 @@ WORKLOADS = {
     "small": ("gauss_product_d2_1e4", lambda W, seed: W.config_small(seed=seed)),
     "corner8": ("corner_peak_d8_1e9", lambda W, seed: W.config_corner8(seed=seed)),
     "gauss8": ("gauss_product_d8_w0.01_1e9", lambda W, seed: W.config_gauss8(seed=seed)),
+    "symmetric8": ("symmetric_corner_peak_d8_1e9", lambda W, seed: W.config_symmetric8(seed=seed)),
 }
 
 
@@ -286,6 +287,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--serve-gib", type=int, default=16)
+    ap.add_argument("--one-d", action="store_true",
+                    help="the m-Cubes1D variant (one shared grid; for symmetric integrands)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -320,8 +323,11 @@ def main():
     if args.workload == "serve":
         return bench_serve(args, M, W, torch)
     name, make = WORKLOADS[args.workload]
-    on_tables = args.workload == "tables"  # the workload the traffic profile was taken on
+    on_tables = args.workload == "tables" and not args.one_d  # where the traffic profile was taken
     prob = make(W, 1)
+    if args.one_d:
+        prob["one_d"] = True
+        name += "_1d"
     bp = M.BoundProblem(prob, args.blocks, args.threads)
     ws = M.Workspace(bp)
     M.prepare(prob, ws, bp=bp)

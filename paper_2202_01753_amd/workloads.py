@@ -128,6 +128,13 @@ def config_corner8(seed=1, rng_seed=8, maxcalls=1_000_000_000, itmax=20, **kw):
                        alpha=1.5, seed=seed, **kw)
 
 
+def config_symmetric8(seed=1, maxcalls=1_000_000_000, itmax=20, **kw):
+    """d=8 corner peak with one coefficient a = 1 on every axis (symmetric in all
+    variables, the m-Cubes1D case), 1e9 samples/iteration, 500 bins."""
+    return symmetric_corner(8, a=1.0, maxcalls=maxcalls, nbins=500, itmax=itmax, alpha=1.5, seed=seed,
+                            **kw)
+
+
 def config_gauss8(seed=1, rng_seed=88, maxcalls=1_000_000_000, itmax=20, **kw):
     """d=8 narrow Gaussian product (w = 0.01), 1e9 samples/iteration, 500 bins."""
     rng = np.random.default_rng(rng_seed)
