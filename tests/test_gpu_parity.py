@@ -212,6 +212,39 @@ def test_deterministic_repeat():
     assert np.allclose(a["hist"], b["hist"], rtol=TOL, atol=0)
 
 
+def test_reentrant_on_two_streams():
+    """Two integrations on two workspaces and two streams at once, from two
+    host threads (ctypes releases the GIL during the calls), give the results
+    each gives alone, to the histogram's rounding."""
+    import threading
+
+    import torch
+
+    probs = [W.config_tables(seed=21, maxcalls=2_000_000, itmax=4),
+             W.corner_peak(6, 3, maxcalls=3_000_000, nbins=200, itmax=5, seed=22)]
+    alone = [M.integrate(p) for p in probs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    out = [None, None]
+    errors = []
+
+    def run(i):
+        try:
+            out[i] = M.integrate(probs[i], stream=streams[i])
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors and all(not t.is_alive() for t in threads)
+    for a, b in zip(out, alone):
+        assert a.iterations == b.iterations
+        assert a.estimate == pytest.approx(b.estimate, rel=TOL, abs=0)
+        assert a.error == pytest.approx(b.error, rel=1e-9, abs=0)
+
+
 def test_integrate_prepared_matches_integrate():
     """mc_integrate_prepared on a workspace filled once by mc_prepare gives
     mc_integrate's results run after run, for both precisions (to rounding:
