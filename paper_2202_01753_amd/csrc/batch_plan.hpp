@@ -108,18 +108,33 @@ inline void split_work(const int64_t *m, const double *cost, int first, int last
     }
 }
 
-// Indices lo..hi-1 of `pieces`, largest work first (ties in index order),
-// appended to order.
+// Indices lo..hi-1 of `pieces`, appended to order from the largest work to
+// the smallest, by a counting sort on the work quantised to 1/kOrderBuckets
+// of the largest piece's (equal buckets keep index order): linear in the
+// number of pieces, and within one bucket of the exact order, which is all
+// that taking the large pieces first needs.
+constexpr int kOrderBuckets = 256;
+
 inline void largest_first(const std::vector<Piece> &pieces, const double *cost, int lo, int hi,
                           std::vector<int32_t> &order) {
+    if (hi <= lo) return;
     std::vector<double> work(hi - lo);
-    for (int k = lo; k < hi; ++k)
+    double top = 0.0;
+    for (int k = lo; k < hi; ++k) {
         work[k - lo] = (double)(pieces[k].t1 - pieces[k].t0) * cost[pieces[k].item];
+        top = std::max(top, work[k - lo]);
+    }
+    std::vector<int32_t> bucket(hi - lo);
+    std::vector<int64_t> count(kOrderBuckets + 1, 0);
+    for (int k = 0; k < hi - lo; ++k) {
+        const int b = top > 0.0 ? std::min(kOrderBuckets - 1, (int)(work[k] / top * kOrderBuckets)) : 0;
+        bucket[k] = kOrderBuckets - 1 - b;  // largest first
+        ++count[bucket[k] + 1];
+    }
+    for (int b = 0; b < kOrderBuckets; ++b) count[b + 1] += count[b];
     const size_t o0 = order.size();
     order.resize(o0 + (hi - lo));
-    std::iota(order.begin() + o0, order.end(), lo);
-    std::stable_sort(order.begin() + o0, order.end(),
-                     [&](int32_t x, int32_t y) { return work[x - lo] > work[y - lo]; });
+    for (int k = 0; k < hi - lo; ++k) order[o0 + count[bucket[k]]++] = lo + k;
 }
 
 }  // namespace plan

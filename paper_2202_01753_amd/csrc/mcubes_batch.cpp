@@ -163,37 +163,54 @@ constexpr int kSegsPerWg = 8;
 // Sub-cubes a segment should at least hold (one per thread of a workgroup, twice).
 constexpr int64_t kMinSegCubes = 2 * kBatchMaxBlock;
 
-StepLayout step_layout(const StepNeed &s, int gcap) {
+// Element counts of one step's tables.
+struct StepCounts {
+    int64_t n = 0;      // integrals
+    int64_t nseg = 0;   // segments
+    int64_t axes = 0;   // (integral, axis) pairs to adjust
+    int64_t admit = 0;  // integrals admitted in the step
+};
+
+// The most a step over these integrals can need: every integral admitted and
+// adjusting, and each launch group's split cutting kSegsPerWg * gcap (+1 for
+// rounding) times.  Admission keeps this within the step area.
+StepCounts worst_counts(const StepNeed &s, int gcap) {
+    return StepCounts{s.n, s.n + kGroups * ((int64_t)kSegsPerWg * gcap + 1), s.sum_d, s.n};
+}
+
+// The step area's regions for the given counts.  Everything up to upload_end
+// is written on the host and uploaded in one copy; the regions whose size
+// depends on the number of segments come last, so that a step uploads only
+// what it uses.
+StepLayout step_layout(const StepCounts &c) {
     StepLayout L{};
-    // each group's split cuts at most kSegsPerWg * gcap (+1 for rounding) times
-    const int64_t nseg = s.n + kGroups * ((int64_t)kSegsPerWg * gcap + 1);
-    L.nseg = nseg;
+    L.nseg = c.nseg;
     size_t off = 0;
     L.items = off;
-    off = align_up(off + sizeof(BatchItem) * s.n);
+    off = align_up(off + sizeof(BatchItem) * c.n);
     L.item_first = off;
-    off = align_up(off + sizeof(int32_t) * (s.n + 1));
+    off = align_up(off + sizeof(int32_t) * (c.n + 1));
     L.flags = off;
-    off = align_up(off + sizeof(uint32_t) * s.n);
+    off = align_up(off + sizeof(uint32_t) * c.n);
     L.queue = off;
     off = align_up(off + sizeof(uint32_t) * kGroups);
-    L.order = off;
-    off = align_up(off + sizeof(int32_t) * nseg);
-    L.segs = off;
-    off = align_up(off + sizeof(BatchSegment) * nseg);
     L.axis_item = off;
-    off = align_up(off + sizeof(int32_t) * 2 * s.sum_d);
+    off = align_up(off + sizeof(int32_t) * 2 * c.axes);
     L.next_grid = off;
-    off = align_up(off + sizeof(double *) * s.n);
+    off = align_up(off + sizeof(double *) * c.n);
     L.admit_recs = off;
-    off = align_up(off + sizeof(AdmitRecord) * s.n);
+    off = align_up(off + sizeof(AdmitRecord) * c.admit);
     L.admit_data = off;
-    off = align_up(off + kConstsMax * s.n);
+    off = align_up(off + kConstsMax * c.admit);
+    L.order = off;
+    off = align_up(off + sizeof(int32_t) * c.nseg);
+    L.segs = off;
+    off = align_up(off + sizeof(BatchSegment) * c.nseg);
     L.upload_end = off;
     L.res = off;
-    off = align_up(off + sizeof(double) * 4 * s.n);
+    off = align_up(off + sizeof(double) * 4 * c.n);
     L.seg_tot = off;
-    off = align_up(off + sizeof(double) * 4 * nseg);
+    off = align_up(off + sizeof(double) * 4 * c.nseg);
     L.total = off;
     return L;
 }
@@ -287,7 +304,7 @@ struct mc_server {
         r->block_bytes = block_layout(*r, &a, &b, &c, &e, &f);
         StepNeed one;
         one.add(*r);
-        if (r->block_bytes > arena_bytes || step_layout(one, gcap).total > step_cap) return MC_EWORKSPACE;
+        if (r->block_bytes > arena_bytes || step_layout(worst_counts(one, gcap)).total > step_cap) return MC_EWORKSPACE;
         *id = r->id;
         queue.push_back(r.get());
         all.emplace(r->id, std::move(r));
@@ -317,7 +334,7 @@ struct mc_server {
             Request *r = queue.front();
             StepNeed grown = need;
             grown.add(*r);
-            if (step_layout(grown, gcap).total > step_cap) break;
+            if (step_layout(worst_counts(grown, gcap)).total > step_cap) break;
             size_t off;
             if (!arena->alloc(r->block_bytes, &off)) break;
             size_t oc, ot, og0, og1, oo;
@@ -398,35 +415,15 @@ struct mc_server {
         const int n = (int)active.size();
 
         char *step_base = ws + arena_bytes;
-        const StepLayout L = step_layout(need, gcap);
-        HIP_TRY(staging.reserve(L.upload_end));
-        std::memset(staging.data(), 0, L.upload_end);
-        BatchItem *items = reinterpret_cast<BatchItem *>(staging.data() + L.items);
-        int32_t *item_first_h = reinterpret_cast<int32_t *>(staging.data() + L.item_first);
-        double **next_grid = reinterpret_cast<double **>(staging.data() + L.next_grid);
-        int32_t *axis_item = reinterpret_cast<int32_t *>(staging.data() + L.axis_item);
+        // per integral: the launch group's LDS, the group ranges, the axes to adjust
         int n_axes = 0, max_nb = 2;
         size_t lds[kGroups] = {};
         int first[kGroups + 1] = {};
         for (int i = 0; i < n; ++i) {
-            Request *r = active[i];
+            const Request *r = active[i];
             const bool adjust = r->it < r->prob.ita;
-            BatchItem &b = items[i];
-            double *grid = reinterpret_cast<double *>(ws + r->off_grid[r->cur]);
-            sample_args(&r->prob, r->g, r->m, r->p, (uint32_t)r->it, adjust, ws + r->off_consts, grid,
-                        r->tables.empty() ? nullptr : ws + r->off_tables, &b.a);
-            b.grid = grid;
-            b.out = reinterpret_cast<double *>(ws + r->off_out);
-            b.alpha = r->prob.alpha;
-            b.refine = adjust ? 1 : 0;
-            next_grid[i] = reinterpret_cast<double *>(ws + r->off_grid[1 - r->cur]);
             if (adjust) {
-                const int axes = r->prob.one_d ? 1 : r->prob.dim;  // m-Cubes1D: axis 0, then copied
-                for (int j = 0; j < axes; ++j) {
-                    axis_item[2 * n_axes] = i;
-                    axis_item[2 * n_axes + 1] = j;
-                    ++n_axes;
-                }
+                n_axes += r->prob.one_d ? 1 : r->prob.dim;  // m-Cubes1D: axis 0, then copied
                 max_nb = std::max(max_nb, r->prob.nbins);
             }
             const int grp = r->group;
@@ -471,32 +468,67 @@ struct mc_server {
             plan::largest_first(segs, costs.data(), seg_lo[grp], (int)segs.size(), order);
         }
         seg_lo[kGroups] = (int)segs.size();
-        if ((int64_t)segs.size() > L.nseg) return MC_EINVAL;  // cannot happen: the layout's bound
-        for (int i = 0; i < n; ++i) item_first_h[i] = item_first[i];
+
+        // this step's tables, packed for the counts it actually has (within
+        // the worst case that admission reserved)
+        const StepCounts counts{n, (int64_t)segs.size(), n_axes, (int64_t)admitted.size()};
+        const StepLayout L = step_layout(counts);
+        if (L.total > step_cap || (int64_t)segs.size() > worst_counts(need, gcap).nseg)
+            return MC_EWORKSPACE;  // cannot happen: admission keeps the worst case within the area
+        HIP_TRY(staging.reserve(L.upload_end));
+        char *up = staging.data();
+        std::memset(up + L.flags, 0, L.axis_item - L.flags);  // flags and queue counters start at 0
+        BatchItem *items = reinterpret_cast<BatchItem *>(up + L.items);
+        int32_t *item_first_h = reinterpret_cast<int32_t *>(up + L.item_first);
+        double **next_grid = reinterpret_cast<double **>(up + L.next_grid);
+        int32_t *axis_item = reinterpret_cast<int32_t *>(up + L.axis_item);
+        int ax = 0;
+        for (int i = 0; i < n; ++i) {
+            Request *r = active[i];
+            const bool adjust = r->it < r->prob.ita;
+            BatchItem &b = items[i];
+            std::memset(&b, 0, sizeof(b));
+            double *grid = reinterpret_cast<double *>(ws + r->off_grid[r->cur]);
+            sample_args(&r->prob, r->g, r->m, r->p, (uint32_t)r->it, adjust, ws + r->off_consts, grid,
+                        r->tables.empty() ? nullptr : ws + r->off_tables, &b.a);
+            b.grid = grid;
+            b.out = reinterpret_cast<double *>(ws + r->off_out);
+            b.alpha = r->prob.alpha;
+            b.refine = adjust ? 1 : 0;
+            next_grid[i] = reinterpret_cast<double *>(ws + r->off_grid[1 - r->cur]);
+            if (adjust) {
+                const int axes = r->prob.one_d ? 1 : r->prob.dim;
+                for (int j = 0; j < axes; ++j) {
+                    axis_item[2 * ax] = i;
+                    axis_item[2 * ax + 1] = j;
+                    ++ax;
+                }
+            }
+            item_first_h[i] = item_first[i];
+        }
         item_first_h[n] = (int32_t)segs.size();
-        BatchSegment *segs_h = reinterpret_cast<BatchSegment *>(staging.data() + L.segs);
+        BatchSegment *segs_h = reinterpret_cast<BatchSegment *>(up + L.segs);
         for (size_t k = 0; k < segs.size(); ++k)
             segs_h[k] = BatchSegment{segs[k].item, 0, segs[k].t0, segs[k].t1};
-        std::memcpy(staging.data() + L.order, order.data(), sizeof(int32_t) * order.size());
-        // the queue counters are zero: the staging buffer is cleared every step
+        std::memcpy(up + L.order, order.data(), sizeof(int32_t) * order.size());
         // admissions of this step: constants into the upload, records for admit_kernel
-        AdmitRecord *recs = reinterpret_cast<AdmitRecord *>(staging.data() + L.admit_recs);
-        size_t adm_off = L.admit_data;
+        AdmitRecord *recs = reinterpret_cast<AdmitRecord *>(up + L.admit_recs);
         for (size_t k = 0; k < admitted.size(); ++k) {
             Request *r = admitted[k];
-            std::memcpy(staging.data() + adm_off, r->consts_img.data(), r->consts_img.size());
+            const size_t src = L.admit_data + k * kConstsMax;
+            std::memcpy(up + src, r->consts_img.data(), r->consts_img.size());
             AdmitRecord &rec = recs[k];
+            std::memset(&rec, 0, sizeof(rec));
             rec.consts = ws + r->off_consts;
             rec.grid = reinterpret_cast<double *>(ws + r->off_grid[0]);
             rec.out = reinterpret_cast<double *>(ws + r->off_out);
-            rec.src = (int64_t)adm_off;
+            rec.src = (int64_t)src;
             rec.const_words = (int32_t)(r->consts_img.size() / 4);
             rec.dim = r->prob.dim;
             rec.nb = r->prob.nbins;
-            adm_off += kConstsMax;
             std::vector<char>().swap(r->consts_img);
         }
-        HIP_TRY(hipMemcpyAsync(step_base, staging.data(), adm_off, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(step_base, up, L.upload_end, hipMemcpyHostToDevice, stream));
         HIP_TRY(launch_admit(reinterpret_cast<const AdmitRecord *>(step_base + L.admit_recs),
                              (int)admitted.size(), step_base, stream));
         admitted.clear();
@@ -669,7 +701,7 @@ mc_status mc_batch_workspace_bytes(const mc_problem *probs, int32_t n, size_t *b
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    *bytes = align_up(arena) + step_layout(need, cus * 4).total;
+    *bytes = align_up(arena) + step_layout(worst_counts(need, cus * 4)).total;
     return MC_OK;
 }
 
