@@ -66,7 +66,7 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float
       two bilinear tables       2 x 21 + 2 products (on top of the Gaussian), both paths
       f J / (m p), finiteness   4                              6 (two widening conversions)
       shifted sums              3 (p-1)/p
-      bin contributions         1 + d addresses (adjusting iterations)
+      bin contributions         1 + d addresses (adjusting iterations; 1 + 1 in m-Cubes1D)
       per sub-cube, / p         variance 5, two compensated additions 14,
                                 digit odometer 4 d, digit conversion d
     """
@@ -85,7 +85,8 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float
         f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + div
     else:
         f = 3 * d + expo + 2 * 21 + 2
-    tail = (6 if fp32 else 4) + 3 * (p - 1) / p + ((1 + d) if adjust else 0) + (19 + 5 * d) / p
+    axes = 1 if prob.get("one_d") else d  # histogram rows (m-Cubes1D: the first axis only)
+    tail = (6 if fp32 else 4) + 3 * (p - 1) / p + ((1 + axes) if adjust else 0) + (19 + 5 * d) / p
     return float(philox + per_axis + f + tail)
 
 

@@ -58,9 +58,8 @@ bool is_fp32(const mc_problem *pr) { return pr->precision == MC_FP32_EVAL; }
 // boundaries per axis; FP32: a float (left, width) pair per bin) and, when
 // collecting bin contributions, the FP64 histogram.
 size_t lds_bytes_of(int d, int nb, bool hist, bool fp32) {
-    const size_t consts = (size_t)kConstStride * d * (fp32 ? sizeof(float) : sizeof(double));
     const size_t grid = fp32 ? (size_t)d * nb * 2 * sizeof(float) : (size_t)d * (nb + 1) * sizeof(double);
-    return consts + grid + (hist ? (size_t)d * nb * sizeof(double) : 0);
+    return grid + (hist ? (size_t)d * nb * sizeof(double) : 0);
 }
 
 mc_status validate(const mc_problem *pr) {

@@ -46,7 +46,7 @@ size_t align_up(size_t v);
 mc_status lattice(int d, int64_t maxcalls, int64_t *g, int64_t *m, int64_t *p);
 bool is_fp32(const mc_problem *pr);
 inline int threads_of(const mc_problem *pr) { return pr->threads ? pr->threads : kDefaultThreads; }
-// LDS of one sampling workgroup (constants, grid, optional FP64 histogram).
+// LDS of one sampling workgroup (grid, optional FP64 histogram).
 size_t lds_bytes_of(int d, int nb, bool hist, bool fp32);
 // Checks a problem before any device work; MC_OK or MC_EINVAL.
 mc_status validate(const mc_problem *pr);

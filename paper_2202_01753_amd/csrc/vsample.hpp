@@ -24,6 +24,13 @@
 
 namespace mcubes {
 
+// Read-only data reached through the constant address space: uniform loads
+// become scalar loads, which the compiler may repeat instead of keeping every
+// value in registers.  Only for memory that nothing writes while the kernel
+// runs.
+template <typename T>
+using Const = __attribute__((address_space(4))) const T;
+
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon et al., SC'11: ten rounds of two 32x32->64 products, with the key
 // advanced by the Weyl constants between rounds.  The key is uniform across
@@ -118,7 +125,8 @@ struct Integrand {
 
     __device__ __forceinline__ Integrand() : acc(F == 2 ? R(1) : R(0)), x0(0), x1(0), x2(0), x3(0) {}
 
-    __device__ __forceinline__ void axis(int j, R xj, const R *cj) {
+    template <typename CP>
+    __device__ __forceinline__ void axis(int j, R xj, CP cj) {
         if constexpr (F == 1 || F == 3) {
             const R t = (xj - cj[3]) * cj[4];
             acc = rfma(t, t, acc);
@@ -181,14 +189,10 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
 
 // ---------------------------------------------------------------- LDS layout
 
-// Per workgroup: per-axis constants (kConstStride values of the evaluation
-// precision per axis), the grid, then (V-Sample only) the d x nb histogram.
-// FP64 keeps each axis's nb+1 boundaries; FP32 keeps per bin its left
-// boundary and width, each rounded once from FP64.
-template <bool F32>
-__host__ __device__ constexpr size_t lds_const_bytes(int d) {
-    return (size_t)kConstStride * d * (F32 ? sizeof(float) : sizeof(double));
-}
+// Per workgroup: the grid, then (V-Sample only) the d x nb histogram.  FP64
+// keeps each axis's nb+1 boundaries; FP32 keeps per bin its left boundary and
+// width, each rounded once from FP64.  (The per-axis constants are read with
+// scalar loads from device memory; see Const.)
 template <bool F32>
 __host__ __device__ constexpr size_t lds_grid_bytes(int d, int nb) {
     return F32 ? (size_t)d * nb * 2 * sizeof(float) : (size_t)d * (nb + 1) * sizeof(double);
@@ -202,26 +206,21 @@ using real_t = typename std::conditional<F32, float, double>::type;
 // The workgroup's LDS regions for an integral of dimension d with nb bins.
 template <bool F32>
 struct LdsView {
-    real_t<F32> *consts;
     real_t<F32> *grid;
     double *hist;
     __device__ LdsView(double *lds, int d, int nb) {
         char *base = reinterpret_cast<char *>(lds);
-        consts = reinterpret_cast<real_t<F32> *>(base);
-        grid = reinterpret_cast<real_t<F32> *>(base + lds_const_bytes<F32>(d));
-        hist = reinterpret_cast<double *>(base + lds_const_bytes<F32>(d) + lds_grid_bytes<F32>(d, nb));
+        grid = reinterpret_cast<real_t<F32> *>(base);
+        hist = reinterpret_cast<double *>(base + lds_grid_bytes<F32>(d, nb));
     }
 };
 
-// Copies the integral's constants and grid into LDS and clears the histogram.
-// Callers synchronise the workgroup afterwards.  (A is SampleArgs, possibly
-// in the constant address space: see the batched kernel.)
+// Copies the integral's grid into LDS and clears the histogram.  Callers
+// synchronise the workgroup afterwards.  (A is SampleArgs, possibly in the
+// constant address space: see the batched kernel.)
 template <int D, bool F32, typename A>
 __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
-    using R = real_t<F32>;
     const int nb = a.nb, row = nb + 1, tid = threadIdx.x, nthr = blockDim.x;
-    const R *gconst = static_cast<const R *>(a.consts);
-    for (int i = tid; i < kConstStride * D; i += nthr) v.consts[i] = gconst[i];
     if constexpr (F32) {
         for (int i = tid; i < D * nb; i += nthr) {
             const int j = i / nb, b = i - j * nb;
@@ -250,8 +249,8 @@ constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 : D <= 11);
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
 // (kPairSamples for a kernel of its own; kernels that inline many cases into
 // one register allocation leave it off).
-template <int F, int D, bool TRACE, bool F32, bool PAIR, typename A>
-__device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, uint64_t t,
+template <int F, int D, bool TRACE, bool F32, bool PAIR, typename A, typename CP>
+__device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad) {
     using R = real_t<F32>;
@@ -261,7 +260,6 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, uin
     const int nb = a.nb, row = nb + 1, rec = 3 * D + 2;
     const R s = R(F32 ? a.s32 : a.s);
     const R last = R(nb - 1);
-    const R *sC = v.consts;
     const R *sG = v.grid;
     double *sH = v.hist;
 
@@ -310,7 +308,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, uin
                     width = B[1] - left;
                 }
                 const R xu = rfma(frac, width, left);
-                const R *cj = sC + kConstStride * j;
+                const auto cj = sC + kConstStride * j;
                 const R xj = rfma(cj[1], xu, cj[0]);
                 J = J * (width * cj[2]);
                 bin[j] = i;
@@ -412,7 +410,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, uin
                     width = B[1] - left;
                 }
                 const R xu = rfma(frac, width, left);
-                const R *cj = sC + kConstStride * j;
+                const auto cj = sC + kConstStride * j;
                 const R xj = rfma(cj[1], xu, cj[0]);
                 J = J * (width * cj[2]);
                 bin[j] = i;
@@ -536,6 +534,10 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     const LdsView<F32> v(lds, D, a.nb);
     load_lds<D, F32>(a, v);
     __syncthreads();
+    // the per-axis constants are the same for every lane: read them through
+    // the constant address space (scalar loads the compiler may repeat), not
+    // from LDS, whose bandwidth the grid reads and histogram atomics need
+    Const<real_t<F32>> *sC = (Const<real_t<F32>> *)a.consts;
 
     uint64_t t = (uint64_t)blockIdx.x * (uint64_t)blockDim.x + (uint64_t)threadIdx.x;
     uint32_t dig[D];
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     bool bad = false;
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>>(a, v, t, dig, It, vt, bad);
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>>(a, v, sC, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         // next sub-cube of this lane: t += stride, digit by digit

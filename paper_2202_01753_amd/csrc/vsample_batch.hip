@@ -19,10 +19,7 @@ namespace {
 
 // The step's tables (items, segments, queue order) are written by the host
 // before the launch and only read during it, so they are read through the
-// constant address space: uniform loads become scalar loads that the
-// compiler may repeat instead of holding every argument in registers.
-template <typename T>
-using Const = __attribute__((address_space(4))) const T;
+// constant address space (Const).
 
 template <int F, int D, bool F32>
 __device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSegment &sg, int si,
@@ -45,7 +42,7 @@ __device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSeg
     bool bad = false;
     while (t < (uint64_t)sg.t1) {
         double It, vt;
-        cube_pass<F, D, false, F32, false>(a, v, t, dig, It, vt, bad);
+        cube_pass<F, D, false, F32, false>(a, v, (Const<real_t<F32>> *)a.consts, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         t += blockDim.x;
