@@ -534,10 +534,13 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     const LdsView<F32> v(lds, D, a.nb);
     load_lds<D, F32>(a, v);
     __syncthreads();
-    // the per-axis constants are the same for every lane: read them through
-    // the constant address space (scalar loads the compiler may repeat), not
-    // from LDS, whose bandwidth the grid reads and histogram atomics need
-    Const<real_t<F32>> *sC = (Const<real_t<F32>> *)a.consts;
+    // the per-axis constants are the same for every lane: read them with
+    // scalar loads (constant address space) rather than from LDS, whose
+    // bandwidth the grid reads and histogram atomics need.  volatile makes
+    // the compiler load each where it is used instead of holding all of them
+    // in scalar registers, which spilled them to VGPR lanes and cost a VALU
+    // read-back per use.
+    volatile Const<real_t<F32>> *sC = (volatile Const<real_t<F32>> *)a.consts;
 
     uint64_t t = (uint64_t)blockIdx.x * (uint64_t)blockDim.x + (uint64_t)threadIdx.x;
     uint32_t dig[D];
