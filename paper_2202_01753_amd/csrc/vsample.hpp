@@ -63,8 +63,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &x0, uint32_t &x1, uint32
 // exponent 0 and mantissa X is 1 + X 2^-52; subtracting 1 - 2^-53 is exact
 // (Sterbenz), so the result is exactly the open-interval uniform.
 __device__ __forceinline__ double uniform53(uint32_t whi, uint32_t wlo) {
-    const uint32_t hi = 0x3FF00000u | (whi >> 12);
-    const uint32_t lo = (whi << 20) | (wlo >> 12);
+    // both words are funnel shifts of a 64-bit pair: {0x3FF, whi} >> 12 is
+    // 0x3FF00000 | (whi >> 12), and {whi, wlo} >> 12 is (whi << 20) | (wlo >> 12)
+    const uint32_t hi = __builtin_amdgcn_alignbit(0x3FFu, whi, 12);
+    const uint32_t lo = __builtin_amdgcn_alignbit(whi, wlo, 12);
     return __hiloint2double((int)hi, (int)lo) - 0x1.fffffffffffffp-1;
 }
 
@@ -73,7 +75,8 @@ __device__ __forceinline__ double uniform53(uint32_t whi, uint32_t wlo) {
 // (2 (w >> 9) + 1) 2^-24: the float with exponent 0 and mantissa w >> 9 is
 // 1 + (w >> 9) 2^-23; subtracting 1 - 2^-24 is exact (Sterbenz).
 __device__ __forceinline__ float uniform24(uint32_t w) {
-    return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
+    // {0x7F, w} >> 9 is 0x3F800000 | (w >> 9)
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9)) - 0x1.fffffep-1f;
 }
 
 // Arithmetic of the evaluation precision R (double for the FP64 path, float
