@@ -92,18 +92,34 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float
 
 # The tables kernel's HBM traffic per launch comes from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs (scaled by a copy-kernel calibration) recorded in its
-# profile summary, together with a digest of the sources the kernel is built
-# from; it is reported only while those sources are unchanged.
+# profile summary, together with a digest of the code (comments excluded) the
+# kernel is built from; it is reported only while that code is unchanged.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "vsample_tables_d6_1e8.md")
 KERNEL_SOURCES = ("paper_2202_01753_amd/csrc/vsample.hpp", "paper_2202_01753_amd/csrc/vsample_tables.hip",
                   "paper_2202_01753_amd/csrc/internal.hpp", "paper_2202_01753_amd/build.py")
 
 
-def kernel_sources_digest() -> str:
+def _code_only(text: str, python: bool) -> str:
+    """The text without comments and with runs of whitespace collapsed, so
+    that editing a comment does not count as changing the kernel."""
+    if python:
+        text = re.sub(r"(?m)^\s*#.*$", "", text)
+        text = re.sub(r'"""[\s\S]*?"""', "", text)
+    else:
+        text = re.sub(r"/\*[\s\S]*?\*/", "", text)
+        text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split())
+
+
+def kernel_sources_digest(root: str = ROOT, read=None) -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(root, rel)) as f:
+                text = f.read()
+        else:
+            text = read(rel)
+        h.update(_code_only(text, rel.endswith(".py")).encode())
     return h.hexdigest()
 
 

@@ -54,9 +54,9 @@ int expected_params(int integrand, int d) {
 
 bool is_fp32(const mc_problem *pr) { return pr->precision == MC_FP32_EVAL; }
 
-// LDS of one sampling workgroup: per-axis constants, the grid (FP64: nb+1
-// boundaries per axis; FP32: a float (left, width) pair per bin) and, when
-// collecting bin contributions, the FP64 histogram.
+// LDS of one sampling workgroup: the grid (FP64: nb+1 boundaries per axis;
+// FP32: a float (left, width) pair per bin) and, when collecting bin
+// contributions, the FP64 histogram.
 size_t lds_bytes_of(int d, int nb, bool hist, bool fp32) {
     const size_t grid = fp32 ? (size_t)d * nb * 2 * sizeof(float) : (size_t)d * (nb + 1) * sizeof(double);
     return grid + (hist ? (size_t)d * nb * sizeof(double) : 0);
@@ -107,7 +107,7 @@ hipError_t allow_lds(const void *fn, size_t bytes) {
     return hipSuccess;
 }
 
-// Per-axis constants in the layout the sampling kernel keeps in LDS.
+// Per-axis constants in the layout the sampling kernels read.
 std::vector<double> axis_constants(const mc_problem *pr) {
     const int d = pr->dim, nb = pr->nbins;
     std::vector<double> c((size_t)kConstStride * d, 0.0);

@@ -52,7 +52,7 @@ size_t lds_bytes_of(int d, int nb, bool hist, bool fp32);
 mc_status validate(const mc_problem *pr);
 // Lets a kernel use more than 64 KB of dynamic LDS (once per kernel and size).
 hipError_t allow_lds(const void *fn, size_t bytes);
-// Per-axis constants (kConstStride doubles per axis) as the kernels keep them in LDS.
+// Per-axis constants (kConstStride doubles per axis) in the layout the kernels read.
 std::vector<double> axis_constants(const mc_problem *pr);
 // The per-integral part of the sampling-kernel arguments (lattice, scales,
 // iteration, pointers into device memory); launch-specific fields are zero.

@@ -45,7 +45,7 @@ struct SampleArgs {
     int32_t sdig[kMaxDim];  // stride in base g, least significant digit first
 };
 
-// Per-axis constants, copied to LDS by every workgroup:
+// Per-axis constants, in device memory (the kernels read them with scalar loads):
 //   [0] lo   [1] span = hi - lo   [2] q = nb * span
 //   [3] Gaussian centre or corner-peak coefficient   [4] Gaussian 1/width   [5] 0
 constexpr int kConstStride = 6;

@@ -4,7 +4,7 @@
 // bounded work and orders them largest first; the workgroups take segments
 // from a shared counter until none is left, so they finish together whatever
 // the actual cost of each integrand.  For each segment the workgroup loads
-// that integral's constants and grid into LDS, samples the segment's cubes
+// that integral's grid into LDS, samples the segment's cubes
 // with the same per-cube code as the single-integral kernel, writes the
 // segment's totals to its own slot and adds its LDS histogram into the
 // integral's.  A second kernel merges every integral's segment totals in
