@@ -150,3 +150,30 @@ def test_batch_one_d_matches_single_path():
         single = M.integrate(p)
         _close(mixed[i], {"estimate": single.estimate, "error": single.error,
                           "iterations": single.iterations, "converged": single.converged})
+
+
+def test_batch_large_lds_groups_and_fp32_tables():
+    """Integrals whose LDS footprint limits the workgroups per CU (d = 10 with
+    500 bins needs 80 KB and runs in the wide-workgroup launch group) and the
+    FP32 table kernel, each the same alone and in a mix with small integrals,
+    and the same as the single-integral path."""
+    probs = [
+        W.gauss_product(10, 31, maxcalls=2_000_000, nbins=500, itmax=3, seed=41),
+        dict(W.corner_peak(9, 32, maxcalls=1_500_000, nbins=480, itmax=3, seed=42), precision="fp32"),
+        W.gauss_tables(6, 33, w_range=(0.1, 0.3), maxcalls=400_000, nbins=150, itmax=4, seed=43,
+                       precision="fp32"),
+        W.gauss_tables(8, 34, w_range=(0.1, 0.3), maxcalls=600_000, nbins=300, itmax=3, seed=44),
+        W.config_small(seed=45),
+        W.corner_peak(3, 35, maxcalls=20_000, nbins=60, itmax=4, seed=46),
+    ]
+    mixed, _ = M.batch_integrate(probs)
+    for i, p in enumerate(probs):
+        # FP32 evaluation can turn an ulp of difference in a boundary (from
+        # the order of the histogram sums, or device vs host pow/log) into a
+        # float rounding of a point, hence the looser bound there
+        tol = 1e-7 if p.get("precision") == "fp32" else MIX_TOL
+        alone, _ = M.batch_integrate([p])
+        _close(mixed[i], alone[0], tol)
+        single = M.integrate(p)
+        _close(mixed[i], {"estimate": single.estimate, "error": single.error,
+                          "iterations": single.iterations, "converged": single.converged}, tol)
