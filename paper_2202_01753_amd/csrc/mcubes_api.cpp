@@ -53,18 +53,44 @@ mc_status blocks_for(const void *fn, int threads, size_t lds, int64_t m, int req
     return MC_OK;
 }
 
+// Workgroup size when the problem leaves it open: of 1024, 512 and 256
+// threads, the one that keeps the most waves resident per CU given the
+// kernel's registers and the adjusting pass's LDS; on a tie the larger, which
+// means fewer workgroups and so fewer histogram partials to merge.
+mc_status pick_threads(const void *fn, size_t lds, int *out) {
+    HIP_TRY(allow_lds(fn, lds));
+    int best = 0, best_waves = -1;
+    for (int t : {1024, 512, 256}) {
+        int per_cu = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, t, lds));
+        const int waves = per_cu * t / 64;
+        if (waves > best_waves) {
+            best_waves = waves;
+            best = t;
+        }
+    }
+    if (best_waves < 1) return MC_EINVAL;
+    *out = best;
+    return MC_OK;
+}
+
 mc_status geometry(const mc_problem *pr, Geometry *geo) {
     mc_status st = validate(pr);
     if (st != MC_OK) return st;
     Geometry G{};
     lattice(pr->dim, pr->maxcalls, &G.g, &G.m, &G.p);
     const int d = pr->dim, nb = pr->nbins;
-    G.threads = threads_of(pr);
     const bool f32 = is_fp32(pr);
     G.lds_adj = lds_bytes_of(d, nb, true, f32);
     G.lds_noadj = lds_bytes_of(d, nb, false, f32);
     const void *fn = sample_kernel(pr->integrand, d, false, f32);
     if (!fn) return MC_EINVAL;
+    if (pr->threads) {
+        G.threads = pr->threads;
+    } else {
+        st = pick_threads(fn, G.lds_adj, &G.threads);
+        if (st != MC_OK) return st;
+    }
     st = blocks_for(fn, G.threads, G.lds_adj, G.m, pr->blocks, &G.blocks_adj);
     if (st != MC_OK) return st;
     st = blocks_for(fn, G.threads, G.lds_noadj, G.m, pr->blocks, &G.blocks_noadj);
