@@ -95,8 +95,10 @@ def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float
 # profile summary, together with a digest of the code (comments excluded) the
 # kernel is built from; it is reported only while that code is unchanged.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "vsample_tables_d6_1e8.md")
+# The kernel and its launch shape (workgroup size and count, chosen on the host).
 KERNEL_SOURCES = ("paper_2202_01753_amd/csrc/vsample.hpp", "paper_2202_01753_amd/csrc/vsample_tables.hip",
-                  "paper_2202_01753_amd/csrc/internal.hpp", "paper_2202_01753_amd/build.py")
+                  "paper_2202_01753_amd/csrc/internal.hpp", "paper_2202_01753_amd/csrc/mcubes_api.cpp",
+                  "paper_2202_01753_amd/csrc/host.cpp", "paper_2202_01753_amd/build.py")
 
 
 def _code_only(text: str, python: bool) -> str:
