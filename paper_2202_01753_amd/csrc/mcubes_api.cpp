@@ -156,6 +156,28 @@ struct Events {
 
 // Runs sampling + finalize and reads the result back.  out_host holds
 // 4 + d*nb doubles.
+// Page-locked staging for the calling thread's passes (grid up, results
+// down), grown on demand and kept until the process ends, so that both copies
+// are direct DMA rather than staged through pageable memory.
+hipError_t pass_stage(size_t bytes, char **out) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) {
+            const hipError_t e = hipHostFree(buf);
+            buf = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
+        const size_t want = std::max(bytes, size_t(1) << 20);
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&buf), want, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        cap = want;
+    }
+    *out = buf;
+    return hipSuccess;
+}
+
 mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t stream,
                    uint32_t iter, bool adjust, const double *h_grid, double *out_host,
                    double *trace, int64_t t0, int64_t t1, Events *ev, double *ms_sample,
@@ -168,8 +190,13 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     a.trace = trace;
     a.t0 = t0;
     a.t1 = t1;
-    HIP_TRY(hipMemcpyAsync(ws + G.off_grid, h_grid, sizeof(double) * d * (nb + 1),
-                           hipMemcpyHostToDevice, stream));
+    const size_t grid_bytes = sizeof(double) * d * (nb + 1);
+    const size_t nout = 4 + (adjust ? (size_t)d * nb : 0);
+    char *stage = nullptr;
+    HIP_TRY(pass_stage(align_up(grid_bytes) + sizeof(double) * nout, &stage));
+    std::memcpy(stage, h_grid, grid_bytes);
+    double *out_stage = reinterpret_cast<double *>(stage + align_up(grid_bytes));
+    HIP_TRY(hipMemcpyAsync(ws + G.off_grid, stage, grid_bytes, hipMemcpyHostToDevice, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[0], stream));
     HIP_TRY(allow_lds(sample_kernel(pr->integrand, d, trace != nullptr, is_fp32(pr)), lds));
     HIP_TRY(launch_sample(pr->integrand, d, blocks, G.threads, lds, stream, a));
@@ -179,9 +206,9 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
                             out_dev, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[2], stream));
     if (adjust && d > 1 && !pr->one_d) AxisPool::get().prime(spin_us);
-    const size_t nout = 4 + (adjust ? (size_t)d * nb : 0);
-    HIP_TRY(hipMemcpyAsync(out_host, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(out_stage, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    std::memcpy(out_host, out_stage, sizeof(double) * nout);
     if (ev) {
         float a_ms = 0.f, b_ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&a_ms, ev->e[0], ev->e[1]));
