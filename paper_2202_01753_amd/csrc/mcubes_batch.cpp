@@ -27,6 +27,8 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <unordered_map>
 
 #include "batch_plan.hpp"
@@ -226,12 +228,18 @@ mc_status validate_batch(const mc_problem *pr) {
 
 // ====================================================================== engine
 
+// Occupancy answers of the batched kernels, shared by every server of the
+// process: (device, kernel, threads, LDS bytes rounded up) -> workgroups per CU.
+constexpr size_t kOccLdsGranule = 512;
+static std::mutex g_occ_mu;
+static std::map<std::tuple<int, int, int, size_t>, int> g_occ;
+
 struct mc_server {
     char *ws = nullptr;
     size_t ws_bytes = 0, arena_bytes = 0, step_cap = 0;
     int32_t max_active = 0;
     hipStream_t stream = nullptr;
-    int cus = 0, gcap = 0;
+    int dev = 0, cus = 0, gcap = 0;
     std::unique_ptr<Arena> arena;
     int64_t next_id = 1;
     std::unordered_map<int64_t, std::unique_ptr<Request>> all;
@@ -239,7 +247,6 @@ struct mc_server {
     std::vector<Request *> active;
     std::vector<int64_t> last_finished;  // ids finished in the last step
     std::vector<Request *> admitted;     // admitted in this step, constants and grid pending
-    std::map<std::pair<size_t, int>, int> occ_cache[kKernels];  // workgroups per CU by (LDS, threads)
     int occ_full[kKernels] = {};  // the register-limited occupancy (256-thread workgroups)
     StepNeed need;  // of the active set
     Pinned staging;    // the step's upload
@@ -254,7 +261,6 @@ struct mc_server {
     }
 
     mc_status init() {
-        int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         gcap = cus * 4;  // 256-thread workgroups: at most 4 per CU at the kernels' register use
@@ -270,17 +276,31 @@ struct mc_server {
 
     // Workgroups of a batched kernel that fit on a CU with the given
     // workgroup size and dynamic LDS (cached: the kernels do not change).
+    // The LDS size is rounded up to kOccLdsGranule before the query, which can
+    // only under-state the occupancy, and the answers are kept for the whole
+    // process: a batch has thousands of distinct footprints, a query costs
+    // microseconds.
     mc_status occupancy(int kern, int threads, size_t lds, int *out) {
-        const auto key = std::make_pair(lds, threads);
-        auto it = occ_cache[kern].find(key);
-        if (it == occ_cache[kern].end()) {
-            int per_cu = 0;
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, batch_kernel(kern >= 2, kern % 2 == 1), threads, lds));
-            it = occ_cache[kern].emplace(key, std::min(per_cu, gcap / cus)).first;
+        const size_t lds_q = (lds + kOccLdsGranule - 1) / kOccLdsGranule * kOccLdsGranule;
+        const auto key = std::make_tuple(dev, kern, threads, lds_q);
+        {
+            std::lock_guard<std::mutex> lk(g_occ_mu);
+            auto it = g_occ.find(key);
+            if (it != g_occ.end()) {
+                *out = it->second;
+                return *out >= 1 ? MC_OK : MC_EINVAL;
+            }
         }
-        *out = it->second;
-        return *out >= 1 ? MC_OK : MC_EINVAL;
+        int per_cu = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, batch_kernel(kern >= 2, kern % 2 == 1), threads, lds_q));
+        per_cu = std::min(per_cu, gcap / cus);
+        {
+            std::lock_guard<std::mutex> lk(g_occ_mu);
+            g_occ.emplace(key, per_cu);
+        }
+        *out = per_cu;
+        return per_cu >= 1 ? MC_OK : MC_EINVAL;
     }
 
     mc_status submit(const mc_problem *pr, int64_t *id) {

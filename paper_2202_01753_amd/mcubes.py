@@ -23,11 +23,10 @@ INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 
 PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
-           "mc_weighted_estimate",
-           "mc_integrate", "mc_integrate_prepared", "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
+           "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared",
+           "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
            "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
-           "mc_server_release",
-           "mc_server_stats", "mc_server_destroy")
+           "mc_server_release", "mc_server_stats", "mc_server_destroy")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -346,13 +345,22 @@ def batch_workspace_bytes(probs) -> int:
     return n.value
 
 
+class BatchProblems:
+    """The mc_problem array of a batch and the host arrays it points into,
+    built once and reusable across batch_integrate calls."""
+
+    def __init__(self, probs):
+        self.bps = [BoundProblem(p) for p in probs]
+        self.arr = _problem_array(self.bps)
+        self.n = len(self.bps)
+
+
 def batch_integrate(probs, stream=None, ws=None):
-    """Runs the problems together; returns (list of result dicts or MCubesError per
-    integral, BatchStats)."""
+    """Runs the problems (a list of problem dicts or a BatchProblems) together;
+    returns (list of result dicts or MCubesError per integral, BatchStats)."""
     torch = _torch()
-    bps = [BoundProblem(p) for p in probs]
-    arr = _problem_array(bps)
-    n = len(bps)
+    bp = probs if isinstance(probs, BatchProblems) else BatchProblems(probs)
+    arr, n = bp.arr, bp.n
     need = C.c_size_t()
     _check(lib().mc_batch_workspace_bytes(arr, n, C.byref(need)), "mc_batch_workspace_bytes")
     if ws is None or ws.numel() < need.value:
