@@ -100,19 +100,36 @@ __device__ __forceinline__ R lerp(R a, R b, R t) {
 }
 
 // Bilinear interpolation in one 256x256 table, node (a,b) at (a/255, b/255),
-// the edge cell extended outside the unit square.
+// the edge cell extended outside the unit square, in two parts: table_cell
+// finds the cell of (x, y) and loads its four nodes, interpolate combines
+// them.  The integrand fetches each table's cell as soon as its two
+// coordinates are known, so the loads are in flight while the remaining axes
+// and the exponential are computed; the arithmetic is that of one bilinear
+// interpolation, in the same order.
 template <typename R>
-__device__ __forceinline__ R bilinear(const R *__restrict__ T, R x, R y) {
+struct TableCell {
+    R t00, t01, t10, t11, tx, ty;
+};
+
+template <typename R>
+__device__ __forceinline__ TableCell<R> table_cell(const R *__restrict__ T, R x, R y) {
     const R ux = x * R(255), uy = y * R(255);
     const R fa = rmin(rmax(rfloor(ux), R(0)), R(254));
     const R fb = rmin(rmax(rfloor(uy), R(0)), R(254));
-    const R tx = ux - fa, ty = uy - fb;
     const int cell = (int)fa * kTableN + (int)fb;
-    const R t00 = T[cell];
-    const R t01 = T[cell + 1];
-    const R t10 = T[cell + kTableN];
-    const R t11 = T[cell + kTableN + 1];
-    return lerp(lerp(t00, t10, tx), lerp(t01, t11, tx), ty);
+    TableCell<R> c;
+    c.tx = ux - fa;
+    c.ty = uy - fb;
+    c.t00 = T[cell];
+    c.t01 = T[cell + 1];
+    c.t10 = T[cell + kTableN];
+    c.t11 = T[cell + kTableN + 1];
+    return c;
+}
+
+template <typename R>
+__device__ __forceinline__ R interpolate(const TableCell<R> &c) {
+    return lerp(lerp(c.t00, c.t10, c.tx), lerp(c.t01, c.t11, c.tx), c.ty);
 }
 
 // The integrand, accumulated axis by axis in ascending order so that the
@@ -121,12 +138,20 @@ __device__ __forceinline__ R bilinear(const R *__restrict__ T, R x, R y) {
 //   corner peak       S = 1 + sum_j a_j x_j by fma; f = 1 / S^(D+1), the power by
 //                     left-to-right binary powering, one correctly rounded division
 //   tables            the Gaussian product times T1(x_1, x_2) times T2(x_3, x_4)
-template <int F, int D, typename R>
+// EARLY (tables only): fetch each table's cell as soon as its coordinates are
+// known rather than at the end; the loads then overlap the remaining axes and
+// the exponential, at the price of registers for the eight nodes.  Kernels
+// that inline many cases into one register allocation leave it off.
+template <int F, int D, typename R, bool EARLY>
 struct Integrand {
     R acc;
-    R x0, x1, x2, x3;  // table coordinates (tables only)
+    R x0, x1, x2, x3;        // table coordinates (tables only)
+    TableCell<R> c1, c2;     // the two tables' cells (tables, EARLY only)
+    const R *T;              // the two tables, one after the other (tables only)
 
-    __device__ __forceinline__ Integrand() : acc(F == 2 ? R(1) : R(0)), x0(0), x1(0), x2(0), x3(0) {}
+    __device__ __forceinline__ explicit Integrand(const void *tables)
+        : acc(F == 2 ? R(1) : R(0)), x0(0), x1(0), x2(0), x3(0), c1(), c2(),
+          T(static_cast<const R *>(tables)) {}
 
     template <typename CP>
     __device__ __forceinline__ void axis(int j, R xj, CP cj) {
@@ -141,6 +166,10 @@ struct Integrand {
             if (j == 1) x1 = xj;
             if (j == 2) x2 = xj;
             if (j == 3) x3 = xj;
+            if constexpr (EARLY) {
+                if (j == 1) c1 = table_cell(T, x0, x1);
+                if (j == 3) c2 = table_cell(T + kTableN * kTableN, x2, x3);
+            }
         }
     }
 
@@ -162,10 +191,9 @@ struct Integrand {
             return R(1) / pw;
         } else {
             static_assert(D >= 4, "table integrand needs four axes");
-            const R *T = static_cast<const R *>(a.tables);
             const R G = rexp(-acc);
-            const R T1 = bilinear(T, x0, x1);
-            const R T2 = bilinear(T + kTableN * kTableN, x2, x3);
+            const R T1 = interpolate(EARLY ? c1 : table_cell(T, x0, x1));
+            const R T2 = interpolate(EARLY ? c2 : table_cell(T + kTableN * kTableN, x2, x3));
             return (G * T1) * T2;
         }
     }
@@ -251,8 +279,8 @@ constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 : D <= 11);
 // contributions to the LDS histogram when collecting them, and records the
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
 // (kPairSamples for a kernel of its own; kernels that inline many cases into
-// one register allocation leave it off).
-template <int F, int D, bool TRACE, bool F32, bool PAIR, typename A, typename CP>
+// one register allocation leave it off).  EARLY: see Integrand.
+template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, typename A, typename CP>
 __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad) {
@@ -286,7 +314,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 w[4 * b + 2] = x2;
                 w[4 * b + 3] = x3;
             }
-            Integrand<F, D, R> fx;
+            Integrand<F, D, R, EARLY> fx(a.tables);
             R J = R(1);
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -387,7 +415,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 w[4 * b + 2] = x2;
                 w[4 * b + 3] = x3;
             }
-            Integrand<F, D, R> fx;
+            Integrand<F, D, R, EARLY> fx(a.tables);
             int bin[D];
             R J = R(1);
 #pragma unroll
@@ -552,7 +580,7 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     bool bad = false;
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>>(a, v, sC, t, dig, It, vt, bad);
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true>(a, v, sC, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         // next sub-cube of this lane: t += stride, digit by digit

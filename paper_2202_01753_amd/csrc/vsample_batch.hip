@@ -44,7 +44,7 @@ __device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSeg
         double It, vt;
         // (plain, not volatile, constant loads: measured faster here, where
         // the cases' shared register allocation is set by other values)
-        cube_pass<F, D, false, F32, false>(a, v, (Const<real_t<F32>> *)a.consts, t, dig, It, vt, bad);
+        cube_pass<F, D, false, F32, false, false>(a, v, (Const<real_t<F32>> *)a.consts, t, dig, It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         t += blockDim.x;
