@@ -239,12 +239,12 @@ def bench_batch(args, M, W, torch):
     print(json.dumps(line))
 
 
-def bench_serve(args, M, W, torch):
-    """A Poisson stream of requests served with continuous batching; reports
-    samples/s over the run and p50/p99 time from arrival to answer."""
-    arrivals, probs = W.served_requests(n=args.requests, rate=args.rate, precision=args.precision)
+def _serve_stream(args, M, torch, arrivals, probs, budget):
+    """Serves the Poisson stream once; returns (stats, wall s, latencies ms, failures)."""
     srv = M.Server(ws_bytes=args.serve_gib * 2**30, arena_bytes=args.serve_gib * 2**30 // 2,
                    max_active=8192)
+    if budget:
+        srv.set_step_budget(budget, args.max_skip)
     # warm-up: a few requests through the server before the clock starts
     for p in probs[:8]:
         srv.submit(dict(p, seed=p["seed"] + 10**6))
@@ -255,6 +255,7 @@ def bench_serve(args, M, W, torch):
         if a == 0 and q == 0:
             break
     torch.cuda.synchronize()
+    base = srv.stats()
     done_at, ids = {}, {}
     nxt, n = 0, len(probs)
     t0 = time.perf_counter()
@@ -272,23 +273,50 @@ def bench_serve(args, M, W, torch):
             time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
     el = time.perf_counter() - t0
     st = srv.stats()
+    for f in ("calls", "steps", "sample_ms", "host_ms", "step_ms"):
+        setattr(st, f, getattr(st, f) - getattr(base, f))
     lat = np.array([done_at[i] - arrivals[i] for i in range(n)]) * 1e3
     fails = 0
     for rid in list(ids):
         state, _, _ = srv.poll(rid)
         fails += state != M.REQ_DONE
     srv.close()
+    return st, el, lat, fails
+
+
+def bench_serve(args, M, W, torch):
+    """A Poisson stream of requests served with continuous batching; reports
+    samples/s over the run and p50/p99 time from arrival to answer, under the
+    step budget (least remaining work first) and, for comparison, with every
+    active request in every step."""
+    arrivals, probs = W.served_requests(n=args.requests, rate=args.rate, precision=args.precision)
+    runs = {}
+    for budget in (args.step_budget, 0) if args.step_budget else (0,):
+        runs[budget] = _serve_stream(args, M, torch, arrivals, probs, budget)
+    st, el, lat, fails = runs[args.step_budget]
+    n = len(probs)
+
+    def summary(st, el, lat, fails):
+        return {"samples_per_s": st.calls / el,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                               "mean": float(lat.mean()), "max": float(lat.max())},
+                "failed": fails, "server_steps": st.steps, "max_active": st.max_active,
+                "sampling_ms": st.sample_ms, "server_host_ms": st.host_ms,
+                "server_step_ms": st.step_ms, "wall_ms": el * 1e3}
+
     line = _base_line(args, "served_poisson", st.calls / el, el * 1e3,
                       "f64" if args.precision == "fp64" else "f32-eval/f64-accumulate",
                       {"requests": n, "rate_per_s": args.rate, "dim": "U{3..10}",
                        "tau_rel": "log-U[1e-5,1e-2]", "maxcalls": "1e5/1e6/1e7 by target",
-                       "nbins": 100, "step": "the whole served stream"})
+                       "nbins": 100, "step_budget_samples": args.step_budget,
+                       "max_skip": args.max_skip, "step": "the whole served stream"})
     line["steps"] = 1
-    line["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                          "mean": float(lat.mean()), "max": float(lat.max())}
-    line["served"] = {"failed": fails, "server_steps": st.steps, "max_active": st.max_active,
-                      "sampling_ms": st.sample_ms, "server_host_ms": st.host_ms,
-                      "server_step_ms": st.step_ms, "wall_ms": el * 1e3}
+    s = summary(st, el, lat, fails)
+    line["latency_ms"] = s.pop("latency_ms")
+    s.pop("samples_per_s")
+    line["served"] = s
+    if args.step_budget:
+        line["every_request_every_step"] = summary(*runs[0])
     print(json.dumps(line))
 
 
@@ -307,6 +335,10 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--serve-gib", type=int, default=16)
+    ap.add_argument("--step-budget", type=int, default=200_000_000,
+                    help="serve: samples per server step, least remaining work first (0: no budget)")
+    ap.add_argument("--max-skip", type=int, default=8,
+                    help="serve: steps a request may be left out in a row under the budget")
     ap.add_argument("--one-d", action="store_true",
                     help="the m-Cubes1D variant (one shared grid; for symmetric integrands)")
     ap.add_argument("--calibrate-copy", action="store_true",

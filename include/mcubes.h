@@ -249,6 +249,21 @@ typedef struct mc_server mc_server;
 
 mc_status mc_server_create(void *d_ws, size_t ws_bytes, size_t arena_bytes, int32_t max_active,
                            void *stream, mc_server **out);
+/* Bounds the work of one step (not in the paper: a scheduling policy of the
+ * serving loop).  samples: the step's budget of integrand samples (m p per
+ * iteration of each request it runs); 0, the default, runs every active
+ * request in every step.  Under a budget a step takes every request left out
+ * max_skip steps in a row, and then, by least estimated remaining work (cost
+ * per iteration times the iterations still expected from the current error
+ * and the target, or 2 before an error estimate exists), each that keeps the
+ * other requests' samples within the budget; an empty step takes the first by
+ * that order.  Short requests then finish in a few short steps instead of
+ * waiting for every long one's iteration, and no request is left out more
+ * than max_skip steps in a row.  Each request's result is the same as without
+ * a budget (its samples do not depend on the schedule; sums may be formed in
+ * another order).  MC_EINVAL for a null server or a negative argument.  Takes
+ * effect from the next step. */
+mc_status mc_server_set_step_budget(mc_server *srv, int64_t samples, int32_t max_skip);
 /* Copies the problem (host arrays included) and queues it.  MC_EWORKSPACE if
  * it could never fit, even alone. */
 mc_status mc_server_submit(mc_server *srv, const mc_problem *prob, int64_t *id);

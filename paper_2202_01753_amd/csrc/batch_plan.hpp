@@ -4,7 +4,9 @@
 //     device workspace (offsets only), with coalescing of free neighbours;
 //   * split_work: cutting a group of integrals' sub-cubes into segments of
 //     bounded work;
-//   * largest_first: the order in which a launch's workgroups take them.
+//   * largest_first: the order in which a launch's workgroups take them;
+//   * expected_iterations, select_for_step: which requests a serving step
+//     runs under a step budget.
 #pragma once
 
 #include <algorithm>
@@ -135,6 +137,65 @@ inline void largest_first(const std::vector<Piece> &pieces, const double *cost, 
     const size_t o0 = order.size();
     order.resize(o0 + (hi - lo));
     for (int k = 0; k < hi - lo; ++k) order[o0 + count[bucket[k]]++] = lo + k;
+}
+
+// Iterations a request of the serving loop is still expected to need, after
+// `it` of at most itmax, with target relative error tau and weighted estimate
+// and error so far.  The error of the weighted average falls as 1/sqrt(k) for
+// a settled grid, so after k >= 2 iterations with relative error e the target
+// needs about k (e/tau)^2 in all.  Before two iterations (no usable error
+// yet) a target-driven request is taken to need only the two the convergence
+// test requires, so that new requests get their first iterations soon;
+// without a target (tau = 0) it runs to itmax.  At least 1, at most what is
+// left.
+inline double expected_iterations(int it, int itmax, double tau, double estimate, double error) {
+    const int left = itmax - it;
+    if (left <= 0) return 1.0;
+    if (tau <= 0.0) return left;
+    if (it < 2 || !(error > 0.0) || !std::isfinite(error) || !(std::fabs(estimate) > 0.0))
+        return std::min(std::max(2 - it, 1), left);
+    const double ratio = error / (tau * std::fabs(estimate));
+    const double need = std::ceil((double)it * ratio * ratio) - it;
+    return std::min<double>(std::max(need, 1.0), left);
+}
+
+// One active request as the step budget sees it.
+struct Candidate {
+    double work;      // estimated remaining work (any unit common to all)
+    int64_t samples;  // samples of its next iteration
+    int32_t skipped;  // steps it has been left out in a row
+    int64_t id;       // arrival order
+};
+
+// Which candidates run in this step under a budget of `budget` samples: every
+// one left out max_skip steps in a row, and then, by least remaining work
+// (ties: arrival order), each that keeps the others' samples within the
+// budget (the overdue ones do not count against it, so they delay no one);
+// if that leaves the step empty, the first by that order.  run[i] is 1 for a
+// candidate that runs.
+inline std::vector<char> select_for_step(const std::vector<Candidate> &c, int64_t budget,
+                                         int32_t max_skip) {
+    std::vector<int> idx(c.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+        if (c[x].work != c[y].work) return c[x].work < c[y].work;
+        return c[x].id < c[y].id;
+    });
+    std::vector<char> run(c.size(), 0);
+    int64_t used = 0;
+    bool any = false;
+    for (int i : idx) {
+        if (c[i].skipped >= max_skip) {
+            run[i] = 1;
+            any = true;
+        } else if (used + c[i].samples <= budget) {
+            run[i] = 1;
+            used += c[i].samples;
+            any = true;
+        }
+    }
+    if (!any && !idx.empty()) run[idx[0]] = 1;
+    return run;
 }
 
 }  // namespace plan

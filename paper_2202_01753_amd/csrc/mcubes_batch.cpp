@@ -92,9 +92,11 @@ struct Request {
     mc_result result{};
     double cost = 0;  // relative work per sub-cube (for the work split)
     int group = 0;    // launch group of the current step
+    int skipped = 0;  // consecutive steps left out under a step budget
 };
 
 bool fp32_of(const Request &r) { return is_fp32(&r.prob); }
+
 int dnb(const Request &r) { return r.prob.dim * r.prob.nbins; }
 
 // Relative work of one sub-cube (p samples), from the per-sample operation
@@ -248,6 +250,8 @@ struct mc_server {
     std::vector<int64_t> last_finished;  // ids finished in the last step
     std::vector<Request *> admitted;     // admitted in this step, constants and grid pending
     int occ_full[kKernels] = {};  // the register-limited occupancy (256-thread workgroups)
+    int64_t step_budget = 0;      // samples per step (0: every active request in every step)
+    int32_t max_skip = 0;         // steps a request may be left out in a row under the budget
     StepNeed need;  // of the active set
     Pinned staging;    // the step's upload
     Pinned tab_stage;  // tables of the integrals admitted in this step
@@ -413,6 +417,32 @@ struct mc_server {
         return MC_OK;
     }
 
+    // Under a step budget: keeps in active the requests this step runs
+    // (plan::select_for_step over their estimated remaining work, cost per
+    // iteration times plan::expected_iterations) and moves the others to idle.
+    void select_for_step(std::vector<Request *> &idle) {
+        std::vector<plan::Candidate> cand;
+        cand.reserve(active.size());
+        for (const Request *r : active) {
+            const double iters =
+                plan::expected_iterations(r->it, r->prob.itmax, r->prob.tau_rel, r->est[0], r->est[1]);
+            cand.push_back(plan::Candidate{r->cost * (double)r->m * iters, r->m * r->p, r->skipped, r->id});
+        }
+        const std::vector<char> run = plan::select_for_step(cand, step_budget, max_skip);
+        std::vector<Request *> now;
+        for (size_t i = 0; i < active.size(); ++i) {
+            Request *r = active[i];
+            if (run[i]) {
+                r->skipped = 0;
+                now.push_back(r);
+            } else {
+                r->skipped += 1;
+                idle.push_back(r);
+            }
+        }
+        active.swap(now);
+    }
+
     mc_status step(int32_t *n_finished) {
         *n_finished = 0;
         last_finished.clear();
@@ -420,6 +450,18 @@ struct mc_server {
         mc_status st = admit();
         if (st != MC_OK) return st;
         if (active.empty()) return MC_OK;
+        std::vector<Request *> idle;  // admitted, not run in this step
+        if (step_budget > 0) select_for_step(idle);
+        mc_status rs = run_step(n_finished, t_start);
+        active.insert(active.end(), idle.begin(), idle.end());
+        need = StepNeed{};
+        for (Request *r : active) need.add(*r);
+        return rs;
+    }
+
+    // One step over the requests in active; the finished ones leave it.
+    mc_status run_step(int32_t *n_finished, std::chrono::steady_clock::time_point t_start) {
+        mc_status st = MC_OK;
         // launch groups: the kernel, then whether the integral's LDS footprint
         // still allows the kernel's register-limited workgroups per CU
         for (Request *r : active) {
@@ -614,8 +656,6 @@ struct mc_server {
             }
         }
         active.swap(still);
-        need = StepNeed{};
-        for (Request *r : active) need.add(*r);
         stats.steps += 1;
         stats.max_active = std::max<int32_t>(stats.max_active, n);
         stats.sample_ms += ms;
@@ -644,6 +684,13 @@ mc_status mc_server_create(void *d_ws, size_t ws_bytes, size_t arena_bytes, int3
     mc_status st = s->init();
     if (st != MC_OK) return st;
     *out = s.release();
+    return MC_OK;
+}
+
+mc_status mc_server_set_step_budget(mc_server *srv, int64_t samples, int32_t max_skip) {
+    if (!srv || samples < 0 || max_skip < 0) return MC_EINVAL;
+    srv->step_budget = samples;
+    srv->max_skip = max_skip;
     return MC_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
            "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared",
            "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
-           "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
+           "mc_server_set_step_budget", "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
            "mc_server_release", "mc_server_stats", "mc_server_destroy")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
@@ -109,6 +109,7 @@ def lib() -> C.CDLL:
             "mc_batch_integrate": ([P, C.c_int32, vp, sz, vp, C.POINTER(Result),
                                     C.POINTER(C.c_int32), C.POINTER(BatchStats)], C.c_int32),
             "mc_server_create": ([vp, sz, sz, C.c_int32, vp, C.POINTER(vp)], C.c_int32),
+            "mc_server_set_step_budget": ([vp, C.c_int64, C.c_int32], C.c_int32),
             "mc_server_submit": ([vp, P, C.POINTER(C.c_int64)], C.c_int32),
             "mc_server_step": ([vp] + [C.POINTER(C.c_int32)] * 3, C.c_int32),
             "mc_server_poll": ([vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(Result),
@@ -394,6 +395,12 @@ class Server:
                                       max_active, _stream(stream), C.byref(h)), "mc_server_create")
         self.h = h
         self._keep = {}
+
+    def set_step_budget(self, samples: int, max_skip: int = 8):
+        """At most `samples` integrand samples per step, least remaining work
+        first; a request waits at most `max_skip` steps (0 samples: no limit)."""
+        _check(lib().mc_server_set_step_budget(self.h, int(samples), int(max_skip)),
+               "mc_server_set_step_budget")
 
     def submit(self, prob) -> int:
         bp = BoundProblem(prob)

@@ -6,6 +6,9 @@
 //   order <n>          then n lines "<item> <t0> <t1> <cost>" -> one line of indices
 //   arena <cap> <k>    then k lines "a <bytes>" or "r <off> <bytes>" -> one line per op
 //                      ("ok <off>", "fail", "released"), then "free <bytes> <ranges>"
+//   select <n> <budget> <max_skip>  then n lines "<work> <samples> <skipped> <id>"
+//                                   -> one line of 0/1 per candidate
+//   iters <k>          then k lines "<it> <itmax> <tau> <estimate> <error>" -> one value per line
 #include <cstdio>
 #include <iostream>
 #include <string>
@@ -67,6 +70,28 @@ int main() {
             }
         }
         std::printf("free %zu %zu\n", a.free_bytes(), a.free_ranges());
+    } else if (cmd == "select") {
+        int n, max_skip;
+        long long budget;
+        std::cin >> n >> budget >> max_skip;
+        std::vector<Candidate> c(n);
+        for (int i = 0; i < n; ++i) {
+            long long samples, id;
+            std::cin >> c[i].work >> samples >> c[i].skipped >> id;
+            c[i].samples = samples;
+            c[i].id = id;
+        }
+        const std::vector<char> run = select_for_step(c, budget, max_skip);
+        for (int i = 0; i < n; ++i) std::printf("%d%s", (int)run[i], i + 1 < n ? " " : "\n");
+    } else if (cmd == "iters") {
+        int k;
+        std::cin >> k;
+        for (int i = 0; i < k; ++i) {
+            int it, itmax;
+            double tau, est, err;
+            std::cin >> it >> itmax >> tau >> est >> err;
+            std::printf("%.17g\n", expected_iterations(it, itmax, tau, est, err));
+        }
     } else {
         return 2;
     }

@@ -160,3 +160,87 @@ def test_arena_matches_first_fit_model(driver, seed):
     ops += [f"r {off} {b}" for off, b in live]
     out = _run(driver, f"arena {cap} {len(ops)}\n" + "\n".join(ops) + "\n").splitlines()
     assert out[-1] == f"free {cap // 256 * 256} 1"
+
+
+# ---------------------------------------------------------------- step budget of the serving loop
+
+def _select(exe, cand, budget, max_skip):
+    text = f"select {len(cand)} {budget} {max_skip}\n" + "".join(
+        f"{w!r} {s} {k} {i}\n" for w, s, k, i in cand)
+    return [int(v) for v in _run(exe, text).split()]
+
+
+def _select_model(cand, budget, max_skip):
+    """Plain model: the overdue all run; the rest by (work, arrival) while the
+    non-overdue samples fit; an empty step takes the first by that order."""
+    order = sorted(range(len(cand)), key=lambda i: (cand[i][0], cand[i][3]))
+    run, used = [0] * len(cand), 0
+    for i in order:
+        w, s, k, _ = cand[i]
+        if k >= max_skip:
+            run[i] = 1
+        elif used + s <= budget:
+            run[i], used = 1, used + s
+    if order and not any(run):
+        run[order[0]] = 1
+    return run
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_select_for_step_matches_model(driver, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 80))
+    cand = [(float(rng.choice([1.0, 2.0, 5.0])) * float(10 ** rng.integers(0, 4)),
+             int(rng.choice([10**5, 10**6, 10**7])), int(rng.integers(0, 6)), int(i))
+            for i in range(n)]
+    budget = int(rng.choice([0, 10**5, 3 * 10**6, 2 * 10**7, 10**9]))
+    max_skip = int(rng.integers(0, 6))
+    got = _select(driver, cand, budget, max_skip)
+    assert got == _select_model(cand, budget, max_skip)
+    assert sum(got) >= 1
+    # everything overdue runs; the others that run fit the budget (or are the only one)
+    for (w, s, k, _), r in zip(cand, got):
+        if k >= max_skip:
+            assert r == 1
+    rest = sum(s for (w, s, k, _), r in zip(cand, got) if r and k < max_skip)
+    assert rest <= budget or sum(got) == 1
+
+
+def test_select_for_step_prefers_short_and_bounds_waiting(driver):
+    # one long request (10 units of work per step) and a stream of short ones:
+    # with the budget the short ones run at once, and the long one still runs
+    # at least once every max_skip + 1 steps
+    budget, max_skip = 3 * 10**6, 3
+    long_req = [1000.0, 10**7, 0, 0]
+    waits, longest_gap, gap = [], 0, 0
+    for step in range(40):
+        shorts = [(1.0, 10**6, 0, 1 + 2 * step), (2.0, 10**6, 0, 2 + 2 * step)]
+        cand = [tuple(long_req)] + shorts
+        run = _select(driver, cand, budget, max_skip)
+        assert run[1] == 1 and run[2] == 1
+        if run[0]:
+            long_req[2] = 0
+            gap = 0
+        else:
+            long_req[2] += 1
+            gap += 1
+        longest_gap = max(longest_gap, gap)
+    assert longest_gap == max_skip
+
+
+def test_expected_iterations(driver):
+    cases = [
+        (0, 10, 1e-3, 0.0, 0.0),      # no estimate yet: the two the test needs
+        (1, 10, 1e-3, 1.0, 0.1),      # one iteration: one more
+        (2, 10, 0.0, 1.0, 0.1),       # no target: all that is left
+        (4, 50, 1e-3, 2.0, 4e-3),     # e = 2e-3: 4 (2)^2 = 16 in all, 12 more
+        (4, 10, 1e-3, 2.0, 4e-3),     # capped by itmax
+        (4, 50, 1e-3, 2.0, 1e-3),     # already below the target: at least one
+        (3, 50, 1e-3, -2.0, 6e-3),    # sign of the estimate does not matter: 3 * 9 = 27, 24 more
+        (2, 50, 1e-3, 0.0, 1e-3),     # zero estimate: as if no estimate
+        (2, 50, 1e-3, 1.0, float("nan")),
+        (50, 50, 1e-3, 1.0, 0.1),     # nothing left
+    ]
+    text = f"iters {len(cases)}\n" + "".join(f"{a} {b} {c!r} {d!r} {e!r}\n" for a, b, c, d, e in cases)
+    got = [float(v) for v in _run(driver, text).split()]
+    assert got == [2.0, 1.0, 8.0, 12.0, 6.0, 1.0, 24.0, 1.0, 1.0, 1.0]

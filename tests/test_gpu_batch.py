@@ -177,3 +177,63 @@ def test_batch_large_lds_groups_and_fp32_tables():
         single = M.integrate(p)
         _close(mixed[i], {"estimate": single.estimate, "error": single.error,
                           "iterations": single.iterations, "converged": single.converged}, tol)
+
+
+def _serve_all(probs, budget=0, max_skip=4, late=()):
+    """Runs probs through a server (late ones submitted after the second
+    step); returns the results by index, the samples the server had taken
+    when each finished, and the stats."""
+    srv = M.Server(ws_bytes=512 * 2**20, arena_bytes=64 * 2**20, max_active=256)
+    if budget:
+        srv.set_step_budget(budget, max_skip)
+    ids = {srv.submit(p): i for i, p in enumerate(probs) if i not in late}
+    out, done_at, steps = {}, {}, 0
+    while len(out) < len(probs):
+        srv.step()
+        steps += 1
+        if steps == 2:
+            ids.update({srv.submit(probs[i]): i for i in late})
+        calls = srv.stats().calls
+        for rid in srv.finished():
+            st, res, status = srv.poll(rid)
+            assert st == M.REQ_DONE and status == M.OK
+            out[ids[rid]] = res
+            done_at[ids[rid]] = calls
+            srv.release(rid)
+        assert steps < 2000
+    s = srv.stats()
+    srv.close()
+    return out, done_at, s
+
+
+def test_server_step_budget_same_results_short_requests_first():
+    # two long requests (many samples per iteration, all iterations) among
+    # short ones; under a budget smaller than one long iteration each result is
+    # the same as without it, and the short requests finish after fewer samples
+    # of the whole stream have been taken
+    probs = _mix(seed=11, n=12)
+    longs = (0, 5)
+    for i in longs:
+        probs[i] = dict(probs[i], maxcalls=2_000_000, itmax=6, tau_rel=0.0)
+    budget, max_skip = 300_000, 2
+    for i in longs:
+        _, m, p = M.shape(probs[i]["dim"], probs[i]["maxcalls"])
+        assert m * p > budget
+    free, at0, s0 = _serve_all(probs, late=(3, 9))
+    capped, at1, s1 = _serve_all(probs, budget=budget, max_skip=max_skip, late=(3, 9))
+    for i in range(len(probs)):
+        _close(capped[i], free[i])
+    assert s1.calls == s0.calls  # the same iterations, in other steps
+    assert s1.steps > s0.steps
+    shorts = [i for i in range(len(probs)) if i not in longs]
+    assert sum(at1[i] for i in shorts) < 0.5 * sum(at0[i] for i in shorts)
+
+
+def test_server_step_budget_rejects_negative():
+    srv = M.Server(ws_bytes=64 * 2**20, arena_bytes=16 * 2**20, max_active=8)
+    with pytest.raises(M.MCubesError):
+        srv.set_step_budget(-1, 4)
+    with pytest.raises(M.MCubesError):
+        srv.set_step_budget(10, -1)
+    srv.set_step_budget(0, 0)
+    srv.close()
