@@ -85,7 +85,8 @@ typedef struct mc_problem {
     uint64_t seed;           /* random-number key */
     int32_t blocks;          /* workgroups of the sampling kernel; 0 = fill the device */
     int32_t threads;         /* threads per workgroup, a multiple of 64 in 64..1024; 0: of 1024,
-                                512 and 256 the one keeping the most waves resident per CU */
+                                768, 512 and 256 the one keeping the most waves resident per
+                                CU (ties to the larger) */
     int32_t one_d;           /* 1: the m-Cubes1D variant (Sec. V): bin contributions of the first
                                 axis only, and its adjusted boundaries shared by every axis; meant
                                 for fully symmetric integrands.  0: separate grids per axis */

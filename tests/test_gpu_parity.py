@@ -169,7 +169,7 @@ def test_lockstep_edge_cases(case):
     _lockstep(case["make"]())
 
 
-@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 7), (256, 0), (1024, 0), (512, 3)])
+@pytest.mark.parametrize("threads,blocks", [(64, 1), (64, 7), (256, 0), (1024, 0), (512, 3), (768, 5)])
 def test_launch_shape_does_not_change_samples(threads, blocks):
     prob = W.corner_peak(4, 12, maxcalls=40_000, nbins=50, itmax=2, seed=77)
     _lockstep(prob, threads=threads, blocks=blocks)
