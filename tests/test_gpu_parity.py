@@ -175,6 +175,23 @@ def test_launch_shape_does_not_change_samples(threads, blocks):
     _lockstep(prob, threads=threads, blocks=blocks)
 
 
+def test_default_launch_shape_follows_occupancy():
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    # d = 8, nb = 500: 64 KB of LDS per workgroup, so two fit per CU, and two of
+    # 768 threads keep more waves resident than one of 1024; the launch takes
+    # four times the resident count (or fewer if the cubes run out first)
+    c8 = W.corner_peak(8, 8, maxcalls=20_000_000, nbins=500, itmax=1)
+    g, m, p = O.shape(8, 20_000_000)
+    r = M.integrate(c8, timing=True)
+    assert (r.threads, r.lds_bytes) == (768, 64064)
+    assert r.blocks == min(4 * 2 * cus, -(-m // 768))
+    # d = 6 tables: one 48 KB workgroup of 1024 threads per CU, launched once per CU
+    t6 = W.config_tables(maxcalls=2_000_000, itmax=1)
+    r6 = M.integrate(t6, timing=True)
+    assert (r6.threads, r6.blocks) == (1024, cus)
+
+
 # ---------------------------------------------------------------- whole runs
 
 def test_integrate_matches_oracle_free_running():
