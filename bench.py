@@ -355,7 +355,7 @@ def main():
         print(json.dumps({"calibration": "device copy", "bytes_each_way": nbytes, "dispatches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
     cpu = None

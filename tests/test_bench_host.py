@@ -1,0 +1,67 @@
+"""Host-side logic of bench.py, on the CPU: the op model's per-sample counts,
+the source digest that gates the recorded HBM traffic, and the refusal of
+more than one GPU."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+from paper_2202_01753_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+B = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(B)
+
+
+def test_op_model_tables_workload():
+    # d = 6 Gaussian x two tables, g = 19, p = 2: 3 Philox blocks (FP64) or 2
+    # (FP32-eval), 20 / 15 operations per axis, the integrand, and the tail
+    prob = W.config_tables()
+    shape = (19, 19 ** 6, 2)
+    assert B.ops_per_sample(prob, shape, adjust=True) == 344.0
+    assert B.ops_per_sample(prob, shape, adjust=True, fp32=True) == 271.0
+    # No-Adjust drops the 1 + d histogram addresses
+    assert B.ops_per_sample(prob, shape, adjust=False) == 344.0 - 7
+
+
+def test_op_model_one_d_keeps_one_histogram_row():
+    prob = W.config_symmetric8()
+    shape = (12, 12 ** 8, 2)
+    sep = B.ops_per_sample(prob, shape, adjust=True)
+    one = B.ops_per_sample(dict(prob, one_d=1), shape, adjust=True)
+    assert sep - one == 8 - 1
+
+
+def test_digest_ignores_comments_and_sees_code():
+    base = {}
+    for rel in B.KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel)) as f:
+            base[rel] = f.read()
+    d0 = B.kernel_sources_digest(read=base.__getitem__)
+    assert d0 == B.kernel_sources_digest()
+    cpp = next(r for r in B.KERNEL_SOURCES if r.endswith(".hpp"))
+    py = next(r for r in B.KERNEL_SOURCES if r.endswith(".py"))
+    edited = dict(base)
+    edited[cpp] += "\n// a note\n/* another\n   note */\n"
+    edited[py] += "\n# a note\n"
+    assert B.kernel_sources_digest(read=edited.__getitem__) == d0
+    edited[cpp] += "\nstatic int extra;\n"
+    assert B.kernel_sources_digest(read=edited.__getitem__) != d0
+
+
+def test_profiled_traffic_only_for_matching_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "profile.md"
+    monkeypatch.setattr(B, "TRAFFIC_PROFILE", str(prof))
+    assert B.profiled_traffic("fp64") is None  # no profile
+    prof.write_text(f"traffic-per-launch fp64=123 fp32=45 sources={B.kernel_sources_digest()}\n")
+    assert (B.profiled_traffic("fp64"), B.profiled_traffic("fp32")) == (123, 45)
+    prof.write_text("traffic-per-launch fp64=123 fp32=45 sources=" + "0" * 64 + "\n")
+    assert B.profiled_traffic("fp64") is None  # taken from other kernel code
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
