@@ -240,6 +240,7 @@ void sample_args(const mc_problem *pr, int64_t g, int64_t m, int64_t p, uint32_t
     a->hist = adjust ? 1 : 0;
     a->kind = pr->integrand * 32 + pr->dim;
     a->one_d = pr->one_d ? 1 : 0;
+    a->hist_copies = 1;
     a->s = (double)nb / (double)g;
     a->s32 = (float)a->s;
     a->inv = 1.0 / (double)(m * p);

@@ -34,6 +34,7 @@ struct SampleArgs {
     int32_t hist_stride;    // doubles between two workgroups' histograms in partials
     int32_t kind;           // integrand id * 32 + dim (dispatch in the batched kernel)
     int32_t one_d;          // nonzero: collect bin contributions of the first axis only
+    int32_t hist_copies;    // LDS histogram copies: 2 = lanes 32-63 of a wave add into a second
     double s;               // nb / g
     float s32;              // nb / g rounded to float (FP32 evaluation)
     int32_t fp32;           // nonzero: FP32 evaluation

@@ -36,6 +36,7 @@ struct Geometry {
     int blocks_adj, blocks_noadj;
     size_t lds_adj, lds_noadj;
     int hist_stride;          // doubles per workgroup histogram (padded)
+    int hist_copies;          // LDS histogram copies in adjusting passes (1 or 2)
     size_t off_consts, off_grid, off_tables, off_partials, off_out, off_flag, total;
 };
 
@@ -100,6 +101,24 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
         st = pick_threads(fn, G.lds_adj, &G.threads);
         if (st != MC_OK) return st;
     }
+    // A second LDS copy of the histogram, for the upper half of each wave,
+    // halves the lanes that add into one bin at once (lanes of a wave share
+    // the strata of all but the fastest axes, so many fall into the same few
+    // bins); taken where the extra LDS keeps as many workgroups resident.
+    G.hist_copies = 1;
+    {
+        const size_t lds2 = G.lds_adj + sizeof(double) * d * (size_t)nb;
+        if (lds2 <= kLdsDynamicLimit) {
+            int per1 = 0, per2 = 0;
+            HIP_TRY(allow_lds(fn, lds2));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, fn, G.threads, G.lds_adj));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, fn, G.threads, lds2));
+            if (per2 >= per1 && per2 > 0) {
+                G.hist_copies = 2;
+                G.lds_adj = lds2;
+            }
+        }
+    }
     st = blocks_for(fn, G.threads, G.lds_adj, G.m, pr->blocks, &G.blocks_adj);
     if (st != MC_OK) return st;
     st = blocks_for(fn, G.threads, G.lds_noadj, G.m, pr->blocks, &G.blocks_noadj);
@@ -137,6 +156,7 @@ void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter,
     a->flag = reinterpret_cast<uint32_t *>(ws + G.off_flag);
     a->stride = (int64_t)blocks * G.threads;
     a->hist_stride = G.hist_stride;
+    a->hist_copies = adjust ? G.hist_copies : 1;
     // the per-lane stride in base g (only d digits are used: a lane that
     // overflows the top digit has left the lattice)
     int64_t rest = a->stride;

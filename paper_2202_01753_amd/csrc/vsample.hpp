@@ -286,7 +286,7 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
         for (int i = tid; i < D * row; i += nthr) v.grid[i] = a.grid[i];
     }
     if (a.hist)
-        for (int i = tid; i < D * nb; i += nthr) v.hist[i] = 0.0;
+        for (int i = tid; i < D * nb * a.hist_copies; i += nthr) v.hist[i] = 0.0;
 }
 
 // Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
@@ -316,7 +316,9 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
     const R s = R(F32 ? a.s32 : a.s);
     const R last = R(nb - 1);
     const R *sG = v.grid;
-    double *sH = v.hist;
+    // with two histogram copies the upper half of each wave adds into the
+    // second, so at most half as many lanes add into one bin at once
+    double *sH = v.hist + (a.hist_copies > 1 && (threadIdx.x & 32) ? D * a.nb : 0);
 
     R cd[D];
 #pragma unroll
@@ -614,7 +616,11 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     block_totals(sI, cI, sV, cV, bad, a.partials + 4 * (size_t)blockIdx.x, a.flag);
     if (a.hist) {
         double *ph = a.partials + 4 * (size_t)gridDim.x + (size_t)blockIdx.x * a.hist_stride;
-        for (int i = threadIdx.x; i < D * a.nb; i += blockDim.x) ph[i] = v.hist[i];
+        const int n = D * a.nb;
+        if (a.hist_copies > 1)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) ph[i] = v.hist[i] + v.hist[n + i];
+        else
+            for (int i = threadIdx.x; i < n; i += blockDim.x) ph[i] = v.hist[i];
     }
 }
 
