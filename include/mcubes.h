@@ -90,14 +90,22 @@ typedef struct mc_problem {
     int32_t one_d;           /* 1: the m-Cubes1D variant (Sec. V): bin contributions of the first
                                 axis only, and its adjusted boundaries shared by every axis; meant
                                 for fully symmetric integrands.  0: separate grids per axis */
+    double chi2_max;         /* the convergence check also requires chi^2/dof <= chi2_max (Sec. V
+                                counts a run as converged only with a small chi^2); 0 selects
+                                MC_CHI2_DOF_DEFAULT, a negative value leaves chi^2 unchecked;
+                                not NaN */
 } mc_problem;
 
+#define MC_CHI2_DOF_DEFAULT 5.0
+
 typedef struct mc_result {
-    double estimate;   /* weighted estimate over the iterations run */
-    double error;      /* its standard deviation */
-    double chi2_dof;   /* chi^2 per degree of freedom (NaN after one iteration) */
+    double estimate;   /* weighted estimate over the iterations run (see mc_weighted_estimate) */
+    double error;      /* its standard deviation; +inf when no iteration saw a non-zero sample */
+    double chi2_dof;   /* chi^2 per degree of freedom (NaN with fewer than two informative
+                          iterations) */
     int32_t iterations;
-    int32_t converged; /* 1 if error <= tau_rel |estimate| after >= 2 iterations */
+    int32_t converged; /* 1 if, after >= 2 iterations, error <= tau_rel |estimate| and
+                          chi2_dof <= the problem's bound */
     int64_t calls;     /* integrand evaluations: iterations * m * p */
 } mc_result;
 
@@ -167,8 +175,13 @@ mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid);
 
 /* Weighted-Estimates (Alg. 2): inverse-variance weighted mean of k iteration
  * results, its standard deviation and chi^2 per degree of freedom, written
- * to h_out[0..2].  Iterations with zero variance, if any, decide the mean
- * alone.  Host only. */
+ * to h_out[0..2].  An iteration with estimate 0 and variance 0 (no sample saw
+ * a non-zero value) carries no information and is left out; chi^2/dof has
+ * n-1 degrees of freedom for n informative iterations (NaN for n < 2).
+ * Informative iterations with zero variance (an integrand constant on every
+ * sub-cube is estimated exactly), if any, decide the mean alone, with
+ * standard deviation 0 and chi^2/dof 0.  With no informative iteration the
+ * result is 0 with standard deviation +inf.  Host only. */
 mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var, double *h_out);
 
 /* The whole m-Cubes run (Alg. 2): iterations of sampling, weighting, bin

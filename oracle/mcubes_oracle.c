@@ -36,9 +36,14 @@
  *   - Bin contributions are reset every iteration.
  *   - Bin adjustment: three-point smoothing, Lepage's compression
  *     ((1 - s_i/S) / ln(S/s_i))^alpha, and equal-share rebinning.
- *   - Weighted estimate: inverse-variance weights over all iterations so far,
- *     chi^2 per degree of freedom about the weighted mean.
- *   - Convergence: at least two iterations and sigma <= tau_rel |I|.
+ *   - Weighted estimate: inverse-variance weights over the iterations so far
+ *     that carry information, chi^2 per degree of freedom about the weighted
+ *     mean.  An iteration whose estimate and variance are both zero (no
+ *     sample saw a non-zero value) carries none and is left out.
+ *   - Convergence (Sec. V counts a run as converged only with a small
+ *     chi^2): at least two iterations, sigma <= tau_rel |I| and
+ *     chi^2/dof <= chi2_max (5 unless the problem sets another bound; a
+ *     negative bound leaves chi^2 unchecked).
  *   - FP32-eval mode (precision 1): the uniform u = (2 (w[j] >> 9) + 1) 2^-24
  *     from the same words, the map and the integrand in single precision
  *     (constants, each bin's left boundary and width, and the tables rounded
@@ -79,7 +84,10 @@ typedef struct {
     uint64_t seed;
     int32_t precision;      /* 0: FP64, 1: FP32 evaluation with FP64 accumulation */
     int32_t one_d;          /* 1: the m-Cubes1D variant */
+    double chi2_max;        /* convergence bound on chi^2/dof: 0 = 5, negative = none */
 } orc_problem;
+
+#define ORC_CHI2_DOF_DEFAULT 5.0
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
@@ -323,6 +331,7 @@ static int validate(const orc_problem *P)
     if (P->maxcalls < 4) return ORC_EINVAL;
     if (P->itmax < 1 || P->ita < 0 || P->ita > P->itmax) return ORC_EINVAL;
     if (!(P->alpha > 0.0) || !(P->tau_rel >= 0.0)) return ORC_EINVAL;
+    if (isnan(P->chi2_max)) return ORC_EINVAL;
     if (P->precision != 0 && P->precision != 1) return ORC_EINVAL;
     if (P->one_d != 0 && P->one_d != 1) return ORC_EINVAL;
     if (params_expected(P->integrand, d) < 0) return ORC_EINVAL;
@@ -518,8 +527,8 @@ int orc_vsample(const orc_problem *P, uint32_t iter, const double *grid, int64_t
                 J = (double)Jf;
                 f = (double)integrand_value_f(P, &K, xf);
             }
-            if (!isfinite(f)) nonfinite = 1;
             double F = f * J;
+            if (!isfinite(F)) nonfinite = 1;
             double Ik = F * inv;
             if (k == 0) {
                 I0 = Ik;
@@ -637,26 +646,43 @@ void orc_refine_1d(int32_t d, int32_t nb, double alpha, const double *hist, doub
     for (int j = 1; j < d; ++j) memcpy(grid + (size_t)j * (nb + 1), grid, sizeof(double) * (nb + 1));
 }
 
-/* Weighted-Estimates: inverse-variance weighted mean of the k iteration
- * estimates, its standard deviation and chi^2 per degree of freedom.       */
+/* Weighted-Estimates: inverse-variance weighted mean of the iteration
+ * estimates, its standard deviation and chi^2 per degree of freedom
+ * (n - 1 degrees of freedom for n informative iterations).
+ * An iteration with estimate 0 and variance 0 saw no non-zero sample: it
+ * says nothing about the integral and is left out.  If an informative
+ * iteration has variance 0 (the integrand is constant on every sub-cube,
+ * so the iteration is exact), the mean of those iterations is the estimate,
+ * with standard deviation 0 and chi^2/dof 0.  Without any informative
+ * iteration the estimate is 0 with an infinite standard deviation.        */
 void orc_weighted(int32_t k, const double *I, const double *var, double *Ibar, double *sigma,
                   double *chi2_dof)
 {
-    int nzero = 0;
+    int n = 0, nzero = 0;
     double zsum = 0.0;
-    for (int i = 0; i < k; ++i)
+    for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0 && I[i] == 0.0) continue;
+        ++n;
         if (var[i] == 0.0) {
             ++nzero;
             zsum = zsum + I[i];
         }
+    }
+    if (n == 0) {
+        *Ibar = 0.0;
+        *sigma = INFINITY;
+        *chi2_dof = NAN;
+        return;
+    }
     if (nzero > 0) {
         *Ibar = zsum / (double)nzero;
         *sigma = 0.0;
-        *chi2_dof = k > 1 ? 0.0 : NAN;
+        *chi2_dof = n > 1 ? 0.0 : NAN;
         return;
     }
     double W = 0.0, WI = 0.0;
     for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0) continue;   /* only the uninformative ones are left */
         double w = 1.0 / var[i];
         W = W + w;
         WI = WI + w * I[i];
@@ -664,12 +690,26 @@ void orc_weighted(int32_t k, const double *I, const double *var, double *Ibar, d
     double mean = WI / W;
     double chi = 0.0;
     for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0) continue;
         double dev = I[i] - mean;
         chi = chi + (dev * dev) / var[i];
     }
     *Ibar = mean;
     *sigma = 1.0 / sqrt(W);
-    *chi2_dof = k > 1 ? chi / (double)(k - 1) : NAN;
+    *chi2_dof = n > 1 ? chi / (double)(n - 1) : NAN;
+}
+
+/* The convergence test of Alg. 2 (Check-Convergence) with the chi^2
+ * condition of Sec. V: at least two iterations, the standard deviation at
+ * most tau_rel times the estimate's magnitude, and chi^2/dof at most the
+ * problem's bound.                                                          */
+static int orc_converged(const orc_problem *P, int k, double Ibar, double sigma, double chi2)
+{
+    if (k < 2 || !(P->tau_rel > 0.0)) return 0;
+    if (!(sigma <= P->tau_rel * fabs(Ibar))) return 0;
+    if (P->chi2_max < 0.0) return 1;
+    double bound = P->chi2_max > 0.0 ? P->chi2_max : ORC_CHI2_DOF_DEFAULT;
+    return chi2 <= bound;
 }
 
 /* The whole m-Cubes run (Alg. 2).
@@ -704,7 +744,7 @@ int orc_integrate(const orc_problem *P, double *res, int64_t *ires, double *it_I
             else
                 orc_refine(d, nb, P->alpha, hist, grid);
         }
-        if (k >= 2 && P->tau_rel > 0.0 && sigma <= P->tau_rel * fabs(Ibar)) {
+        if (orc_converged(P, k, Ibar, sigma, chi2)) {
             converged = 1;
             break;
         }

@@ -8,8 +8,9 @@ A problem is a plain dict with the keys ``integrand`` (one of "const",
 "gauss_product", "corner_peak", "gauss_tables"), ``params``, ``tables``
 (or None), ``dim``, ``lo``, ``hi``, ``maxcalls``, ``nbins``, ``itmax``,
 ``ita``, ``alpha``, ``tau_rel``, ``seed`` and optionally ``precision``
-("fp64", the default, or "fp32" for FP32 evaluation with FP64 accumulation)
-and ``one_d`` (True for the m-Cubes1D variant).
+("fp64", the default, or "fp32" for FP32 evaluation with FP64 accumulation),
+``one_d`` (True for the m-Cubes1D variant) and ``chi2_max`` (the bound on
+chi^2/dof of the convergence check: 0, the default, means 5; negative, none).
 """
 from __future__ import annotations
 
@@ -50,6 +51,7 @@ class _Problem(C.Structure):
         ("seed", C.c_uint64),
         ("precision", C.c_int32),
         ("one_d", C.c_int32),
+        ("chi2_max", C.c_double),
     ]
 
 
@@ -129,7 +131,7 @@ class _Bound:
             int(prob["itmax"]), int(prob.get("ita", prob["itmax"])), float(prob["alpha"]),
             float(prob.get("tau_rel", 0.0)), int(prob["seed"]) & (2**64 - 1),
             1 if prob.get("precision", "fp64") == "fp32" else 0,
-            1 if prob.get("one_d", False) else 0)
+            1 if prob.get("one_d", False) else 0, float(prob.get("chi2_max", 0.0)))
 
 
 def philox4x32_10(ctr, key):

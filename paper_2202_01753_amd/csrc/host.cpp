@@ -88,6 +88,7 @@ mc_status validate(const mc_problem *pr) {
     if (pr->itmax < 1 || pr->ita < 0 || pr->ita > pr->itmax) return MC_EINVAL;
     if (!(pr->alpha > 0.0) || !std::isfinite(pr->alpha)) return MC_EINVAL;
     if (!(pr->tau_rel >= 0.0) || !std::isfinite(pr->tau_rel)) return MC_EINVAL;
+    if (std::isnan(pr->chi2_max)) return MC_EINVAL;
     const int th = threads_of(pr);
     if (pr->blocks < 0 || th < 64 || th > kMaxBlock || th % 64 != 0) return MC_EINVAL;
     return MC_OK;
@@ -191,22 +192,35 @@ void refine_1d(int d, int nb, double alpha, const double *hist, double *grid) {
     for (int j = 1; j < d; ++j) std::copy(grid, grid + nb + 1, grid + (size_t)j * (nb + 1));
 }
 
+// Iterations with I = 0 and var = 0 saw no non-zero sample and carry no
+// information, so they take no part; among the others an exact iteration
+// (var = 0) decides the mean alone.
 void weighted(int k, const double *I, const double *var, double *out) {
-    int zeros = 0;
-    double zsum = 0.0;
-    for (int i = 0; i < k; ++i)
+    int used = 0, exact = 0;
+    double exact_sum = 0.0;
+    for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0 && I[i] == 0.0) continue;
+        ++used;
         if (var[i] == 0.0) {
-            ++zeros;
-            zsum = zsum + I[i];
+            ++exact;
+            exact_sum = exact_sum + I[i];
         }
-    if (zeros) {
-        out[0] = zsum / (double)zeros;
+    }
+    if (used == 0) {
+        out[0] = 0.0;
+        out[1] = INFINITY;
+        out[2] = NAN;
+        return;
+    }
+    if (exact) {
+        out[0] = exact_sum / (double)exact;
         out[1] = 0.0;
-        out[2] = k > 1 ? 0.0 : NAN;
+        out[2] = used > 1 ? 0.0 : NAN;
         return;
     }
     double wsum = 0.0, wisum = 0.0;
     for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0) continue;
         const double w = 1.0 / var[i];
         wsum = wsum + w;
         wisum = wisum + w * I[i];
@@ -214,12 +228,21 @@ void weighted(int k, const double *I, const double *var, double *out) {
     const double mean = wisum / wsum;
     double chi = 0.0;
     for (int i = 0; i < k; ++i) {
+        if (var[i] == 0.0) continue;
         const double dv = I[i] - mean;
         chi = chi + (dv * dv) / var[i];
     }
     out[0] = mean;
     out[1] = 1.0 / std::sqrt(wsum);
-    out[2] = k > 1 ? chi / (double)(k - 1) : NAN;
+    out[2] = used > 1 ? chi / (double)(used - 1) : NAN;
+}
+
+bool check_convergence(const mc_problem *pr, int k, const double *est) {
+    if (k < 2 || !(pr->tau_rel > 0.0)) return false;
+    if (!(est[1] <= pr->tau_rel * std::fabs(est[0]))) return false;
+    if (pr->chi2_max < 0.0) return true;
+    const double bound = pr->chi2_max > 0.0 ? pr->chi2_max : MC_CHI2_DOF_DEFAULT;
+    return est[2] <= bound;  // false for NaN (fewer than two informative iterations)
 }
 
 

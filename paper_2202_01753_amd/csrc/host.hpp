@@ -69,6 +69,9 @@ void refine(int d, int nb, double alpha, const double *hist, double *grid);
 void refine_1d(int d, int nb, double alpha, const double *hist, double *grid);
 // Weighted-Estimates over k iterations: out = [mean, sigma, chi2/dof].
 void weighted(int k, const double *I, const double *var, double *out);
+// Check-Convergence with the chi^2 condition: k >= 2 iterations, est[1] <=
+// tau_rel |est[0]| and est[2] (chi^2/dof) within the problem's bound.
+bool check_convergence(const mc_problem *pr, int k, const double *est);
 
 // A few host threads that take the axes of one bin adjustment in parallel
 // (axes are independent, so the result does not depend on the split).  The

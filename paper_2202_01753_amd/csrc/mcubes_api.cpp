@@ -421,7 +421,7 @@ mc_status integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *s
             else
                 refine(d, nb, prob->alpha, buf.data() + 4, grid.data());
         }
-        if (k >= 2 && prob->tau_rel > 0.0 && est[1] <= prob->tau_rel * std::fabs(est[0])) {
+        if (check_convergence(prob, k, est)) {
             converged = 1;
             break;
         }

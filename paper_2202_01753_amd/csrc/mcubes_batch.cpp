@@ -645,8 +645,7 @@ struct mc_server {
             r->it += 1;
             weighted(r->it, r->Is.data(), r->Vs.data(), r->est);
             if (adjust) r->cur = 1 - r->cur;
-            const bool conv = r->it >= 2 && r->prob.tau_rel > 0.0 &&
-                              r->est[1] <= r->prob.tau_rel * std::fabs(r->est[0]);
+            const bool conv = check_convergence(&r->prob, r->it, r->est);
             if (conv || r->it >= r->prob.itmax) {
                 r->converged = conv ? 1 : 0;
                 finish(r, MC_REQ_DONE, MC_OK);

@@ -378,13 +378,14 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
             }
             const R f = fx.value(a);
-            bad |= !isfinite(f);
             if (traced) {
                 double *r = a.trace + ((t - a.t0) * (uint64_t)a.p + k) * rec;
                 r[3 * D] = (double)J;
                 r[3 * D + 1] = (double)f;
             }
+            // f J, not f alone: in FP32 evaluation the Jacobian can overflow
             const double Fv = (double)f * (double)J;
+            bad |= !isfinite(Fv);
             return Fv * a.inv;
         };
         // shifted sums in sample order
@@ -480,8 +481,8 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
             }
             const R f = fx.value(a);
-            bad |= !isfinite(f);
             const double Fv = (double)f * (double)J;
+            bad |= !isfinite(Fv);
             const double Ik = Fv * a.inv;
             if (k == 0) {
                 I0 = Ik;

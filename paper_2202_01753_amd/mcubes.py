@@ -57,6 +57,7 @@ class Problem(C.Structure):
         ("blocks", C.c_int32),
         ("threads", C.c_int32),
         ("one_d", C.c_int32),
+        ("chi2_max", C.c_double),
     ]
 
 
@@ -163,7 +164,7 @@ class BoundProblem:
             precision=PRECISIONS[prob.get("precision", "fp64")],
             alpha=float(prob["alpha"]), tau_rel=float(prob.get("tau_rel", 0.0)),
             seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads),
-            one_d=1 if prob.get("one_d", False) else 0)
+            one_d=1 if prob.get("one_d", False) else 0, chi2_max=float(prob.get("chi2_max", 0.0)))
 
     @property
     def ref(self):

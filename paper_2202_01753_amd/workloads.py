@@ -9,8 +9,9 @@ A problem is a plain dict with the keys ``integrand`` ("const",
 ``tables`` (float64 of 2*256*256, or None), ``dim``, ``lo``, ``hi``,
 ``maxcalls``, ``nbins``, ``itmax``, ``ita``, ``alpha``, ``tau_rel``,
 ``seed`` (the sampling seed, separate from the parameter seed) and
-``precision`` ("fp64", or "fp32" for FP32 evaluation with FP64 accumulation)
-and ``one_d`` (True: the m-Cubes1D variant, one grid shared by all axes).
+``precision`` ("fp64", or "fp32" for FP32 evaluation with FP64 accumulation),
+``one_d`` (True: the m-Cubes1D variant, one grid shared by all axes) and
+``chi2_max`` (bound on chi^2/dof for convergence; 0 selects the default).
 
 Parameter layouts:
   const          [v]
@@ -26,7 +27,7 @@ TABLE_N = 256
 
 
 def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=None, hi=None,
-             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64", one_d=False):
+             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64", one_d=False, chi2_max=0.0):
     return {
         "integrand": integrand,
         "params": np.ascontiguousarray(params, dtype=np.float64),
@@ -43,6 +44,7 @@ def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=
         "seed": int(seed),
         "precision": precision,
         "one_d": bool(one_d),
+        "chi2_max": float(chi2_max),
     }
 
 

@@ -85,6 +85,12 @@ def test_weighted_matches_oracle_bit_for_bit():
         assert (np.isnan(a[2]) and np.isnan(b[2])) or a[2] == b[2]
     V[3] = 0.0
     assert M.weighted_estimate(I, V) == O.weighted(I, V)
+    # iterations without information (I = 0 and var = 0) are left out alike
+    for I, V in [([0.0, 3.0, 5.0], [0.0, 1.0, 1.0]), ([0.0, 2.0], [0.0, 0.5]),
+                 ([0.0, 0.0, 0.0], [0.0, 0.0, 0.0]), ([0.0, 2.5, 1.5], [0.0, 0.0, 2.0])]:
+        a, b = M.weighted_estimate(I, V), O.weighted(I, V)
+        assert a[:2] == b[:2]
+        assert (np.isnan(a[2]) and np.isnan(b[2])) or a[2] == b[2]
 
 
 def _bad_problems():

@@ -381,6 +381,21 @@ def test_weighted_hand_cases():
     assert (I, s, c) == (4.0, 0.0, 0.0)
 
 
+
+def test_weighted_leaves_out_iterations_without_information():
+    """An iteration with estimate 0 and variance 0 saw no non-zero sample; it
+    must not pass for an exact result (which would stop the run at 0 +- 0)."""
+    assert O.weighted([0.0, 3.0, 5.0], [0.0, 1.0, 1.0]) == O.weighted([3.0, 5.0], [1.0, 1.0])
+    I, s, c = O.weighted([3.0, 5.0], [1.0, 1.0])
+    assert (I, c) == (4.0, 2.0) and s == pytest.approx(math.sqrt(0.5), rel=1e-15)
+    I, s, c = O.weighted([0.0, 0.0, 0.0], [0.0, 0.0, 0.0])
+    assert I == 0.0 and s == math.inf and math.isnan(c)
+    I, s, c = O.weighted([0.0, 2.0], [0.0, 0.5])  # one informative iteration: no chi^2
+    assert I == 2.0 and s == pytest.approx(math.sqrt(0.5), rel=1e-15) and math.isnan(c)
+    # an exact iteration still decides the mean beside uninformative ones
+    assert O.weighted([0.0, 2.5, 2.5], [0.0, 0.0, 0.0]) == (2.5, 0.0, 0.0)
+
+
 # ---------------------------------------------------------------- whole runs
 
 @pytest.mark.parametrize("make", [
@@ -417,6 +432,116 @@ def test_coverage_protocol():
     assert conv >= 0.9 * n
     assert hits / n > 0.85
     assert 0.6 < np.nanmean(chis) < 1.5
+
+
+def test_convergence_needs_a_small_chi2():
+    """Sec. V counts a run as converged only with an appropriately small
+    chi^2: every converged run of the coverage set has chi^2/dof within the
+    default bound 5, lifting the bound converges at least the same runs (and
+    those at the same iteration or earlier), and a bound of 1e-9 lets only
+    exact (chi^2 = 0) runs converge."""
+    base = W.gauss_product(2, 77, maxcalls=4000, nbins=50, itmax=12, tau_rel=2e-3)
+    blocked = 0
+    for s in range(60):
+        base["seed"] = 500 + s
+        r = O.integrate(dict(base))
+        free = O.integrate(dict(base, chi2_max=-1.0))
+        tight = O.integrate(dict(base, chi2_max=1e-9))
+        if r["converged"]:
+            assert r["chi2_dof"] <= 5.0
+            assert free["converged"] and free["iterations"] <= r["iterations"]
+        blocked += free["converged"] and free["iterations"] < r["iterations"]
+        assert not tight["converged"]
+    assert blocked < 30  # the bound is not so tight that it blocks typical runs
+
+
+def test_narrow_gaussian_d8_is_not_reported_converged():
+    """The w = 0.01 Gaussian product in d = 8 (integral ~1e-14) at 1e6 samples per
+    iteration: from equal bins almost no sample reaches the peak, the
+    iteration estimates climb by tens of orders of magnitude as the grid
+    creeps towards it, and the run must not claim convergence.  In FP32
+    evaluation every exponential underflows, so no iteration carries
+    information: the result is 0 with an infinite error, not 0 +- 0."""
+    for precision in ("fp64", "fp32"):
+        prob = W.config_gauss8(maxcalls=1_000_000, itmax=6, tau_rel=1e-3, precision=precision)
+        r = O.integrate(prob)
+        assert not r["converged"] and r["iterations"] == 6
+        assert r["error"] >= 0.5 * abs(r["estimate"])
+        assert abs(r["estimate"]) < 1e-3 * CF.exact(prob)
+    assert r["estimate"] == 0.0 and r["error"] == math.inf
+
+
+def test_paper_table1_normalised_gaussian():
+    """Table 1's second integral: the sigma-normalised 9-D Gaussian (sigma = 0.01)
+    on (-1, 1)^9, true value 1.  From equal bins almost every sample
+    underflows (the peak fills ~1e-8 of the volume at double precision), so
+    the passes start from the grid whose bins hold equal Gaussian mass
+    (quantiles of N(0, sigma^2)); the estimator is unbiased on any grid, so
+    three passes with the bin adjustment in between must land within four
+    standard deviations of 1.  A dropped factor of the map (nb, H - L, a bin
+    width) would be off by orders of magnitude."""
+    from scipy.stats import norm
+
+    sig, d, nb = 0.01, 9, 200
+    w = sig * math.sqrt(2.0)
+    scale = (1.0 / (sig * math.sqrt(2.0 * math.pi))) ** d  # exp(-x^2/(2 sig^2)) = exp(-(x/w)^2)
+    prob = W._problem("gauss_product", np.concatenate([np.zeros(d), np.full(d, w)]), d, 1_000_000,
+                      nb, 3, lo=-np.ones(d), hi=np.ones(d), alpha=1.5, seed=1)
+    row = np.concatenate([[0.0], (norm.ppf(np.arange(1, nb) / nb) * sig + 1.0) / 2.0, [1.0]])
+    grid = np.tile(row, d)
+    Is, Vs = [], []
+    for it in range(3):
+        r = O.vsample(prob, it, grid, hist=True)
+        Is.append(r["I"] * scale)
+        Vs.append(r["var"] * scale**2)
+        grid = O.refine(d, nb, 1.5, r["hist"], grid)
+    est, err, chi2 = O.weighted(Is, Vs)
+    assert err < 0.01
+    assert abs(est - 1.0) <= 4 * err
+    assert chi2 < 5.0
+
+
+def test_resume_reproduces_the_uninterrupted_run(tmp_path):
+    """A run's whole state after k iterations is its grid and the per-iteration
+    (I_i, var_i): stopping after 5 iterations, saving that state and going on
+    from it for 5 more gives the 10-iteration run bit for bit, because every
+    random number is keyed by (seed, iteration, cube, sample)."""
+    prob = W.corner_peak(4, 9, maxcalls=40_000, nbins=60, itmax=10, ita=7, seed=12)
+    whole = O.integrate(prob)
+    d, nb = prob["dim"], prob["nbins"]
+
+    def run(it0, it1, grid, Is, Vs):
+        for it in range(it0, it1):
+            adjust = it < prob["ita"]
+            r = O.vsample(prob, it, grid, hist=adjust)
+            Is.append(r["I"])
+            Vs.append(r["var"])
+            if adjust:
+                grid = O.refine(d, nb, prob["alpha"], r["hist"], grid)
+        return grid
+
+    Is, Vs = [], []
+    grid = run(0, 5, O.init_grid(d, nb), Is, Vs)
+    np.savez(tmp_path / "state.npz", grid=grid, I=np.array(Is), V=np.array(Vs))
+    st = np.load(tmp_path / "state.npz")
+    Is, Vs = list(st["I"]), list(st["V"])
+    grid = run(5, 10, st["grid"], Is, Vs)
+    assert np.array_equal(np.array(Is), whole["it_I"]) and np.array_equal(np.array(Vs), whole["it_var"])
+    assert np.array_equal(grid, whole["grid"])
+    assert O.weighted(Is, Vs) == (whole["estimate"], whole["error"], whole["chi2_dof"])
+
+
+def test_nonfinite_jacobian_is_reported():
+    """In FP32 evaluation the Jacobian prod_j nb w_j (H_j - L_j) is a float: at
+    d = 12 on (0, 1e4)^12 it is 1e48 and overflows, so f J is not finite even
+    where f is; the pass must report it.  The FP64 pass of the same problem
+    is finite."""
+    d = 12
+    prob = W.symmetric_corner(d, a=1.0, maxcalls=2**13, nbins=8, itmax=1, lo=np.zeros(d),
+                              hi=np.full(d, 1e4))
+    assert O.vsample(prob, 0, O.init_grid(d, 8), check=False)["status"] == O.OK
+    r = O.vsample(dict(prob, precision="fp32"), 0, O.init_grid(d, 8), check=False)
+    assert r["status"] == O.ENONFINITE
 
 
 def test_invalid_problems_rejected():
