@@ -1,7 +1,8 @@
 """Throughput of the m-Cubes VEGAS sampling path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload tables|corner8|gauss8|small|batch|serve] [--precision fp64|fp32]
+                    [--workload tables|corner8|gauss8|small|symmetric8|batch|serve]
+                    [--precision fp64|fp32] [--no-cpu-baseline] [--no-corner8]
 
 One step is one complete m-Cubes run (mc_integrate_prepared: every
 iteration of sampling kernel + fixed-order reduction + read-back + host
@@ -9,15 +10,22 @@ weighting, bin adjustment and convergence check) on the workload's synthetic
 inputs; the workspace is allocated and the integrand's constants and tables
 are uploaded (mc_prepare) before the timed region, so the inputs are resident
 in device memory when it starts.  `value` is integrand samples per second
-over the K timed steps (iterations * m * p per step).
+over the K timed steps (iterations * m * p per step) of the FP64 path; the
+FP32-evaluation path of the same workload, and the time of one run to a 1e-3
+relative error in both, are reported beside it.  The default (d = 6 tables)
+run also measures the d = 8 corner peak at 1e9 samples per iteration, the
+largest single-GPU configuration, in both precisions.
 
 The roofline entry is for the sampling kernel: its average launch duration
 comes from HIP events recorded by the library on the launch stream, and its
 algorithmic work is the per-sample VALU lane-operation count of the method's
 steps (one issue slot per full-rate instruction), times the samples per launch,
-against the chip's VALU issue rate.  The CPU baseline times the FP64 oracle on
-bounded blocks of sub-cubes of the same workload, on one core and on one
-process per host core (at most 16), before the GPU is used.
+against the chip's VALU issue rate.  Where the kernel's rocprofv3 summary was
+taken from the same code, its measured VALU instructions per sample, issue
+ratio and HBM traffic are attached.  The CPU baseline times the FP64 oracle
+on this host, on one core and on one process per usable CPU (at most 16, one
+GPU's share of the host), before the GPU is used, including one run to a
+1e-3 relative error.
 """
 from __future__ import annotations
 
@@ -125,17 +133,32 @@ def kernel_sources_digest(root: str = ROOT, read=None) -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(kind: str):
-    """HBM bytes per launch of the tables kernel ('fp64' or 'fp32') from the
-    profile summary, or None if absent or taken from other kernel sources."""
+def profiled(kind: str):
+    """Figures of the tables kernel ('fp64' or 'fp32') recorded in its profile
+    summary: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE), VALU lane-
+    instructions per sample and the VALU issue ratio (SQ_INSTS_VALU,
+    SQ_BUSY_CYCLES), or None where absent or taken from other kernel sources."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
+    digest = kernel_sources_digest()
+    out = {}
     m = re.search(r"traffic-per-launch fp64=(\d+) fp32=(\d+) sources=([0-9a-f]{64})", text)
-    if not m or m.group(3) != kernel_sources_digest():
-        return None
-    return int(m.group(1) if kind == "fp64" else m.group(2))
+    if m and m.group(3) == digest:
+        out["traffic"] = int(m.group(1) if kind == "fp64" else m.group(2))
+    m = re.search(r"valu-per-sample fp64=([0-9.]+)/([0-9.]+) fp32=([0-9.]+)/([0-9.]+) "
+                  r"sources=([0-9a-f]{64})", text)
+    if m and m.group(5) == digest:
+        i = 1 if kind == "fp64" else 3
+        out["valu_insts_per_sample"] = float(m.group(i))
+        out["valu_issue_ratio"] = float(m.group(i + 1))
+    return out or None
+
+
+def profiled_traffic(kind: str):
+    """HBM bytes per launch of the tables kernel from its profile summary, or None."""
+    return (profiled(kind) or {}).get("traffic")
 
 
 WORKLOADS = {
@@ -149,46 +172,102 @@ WORKLOADS = {
 }
 
 
-def _oracle_pass(job):
-    """One worker of the CPU baseline: the oracle's V-Sample over sub-cubes [t0, t1)."""
-    prob, t0, t1 = job
+def _oracle_block(job):
+    """One worker of the CPU baseline: the oracle's V-Sample over sub-cubes
+    [t0, t1) of iteration `it` on `grid`; returns (I, var, histogram or None, s)."""
+    prob, it, grid, t0, t1, hist = job
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
 
-    grid = O.init_grid(prob["dim"], prob["nbins"])
     t = time.perf_counter()
-    O.vsample(prob, 0, grid, t0, t1, hist=True)
-    return time.perf_counter() - t
+    r = O.vsample(prob, it, grid, t0, t1, hist=hist)
+    return r["I"], r["var"], r["hist"], time.perf_counter() - t
 
 
-def cpu_baseline(prob, target_s: float = 6.0, max_workers: int = 16):
-    """Times the oracle's V-Sample (iteration 0, uniform grid, histogram on) on
-    the first sub-cubes of the workload: on one core, then on one process per
-    host core (at most max_workers, each on its own block of sub-cubes).  Runs
-    before the GPU is touched, so the worker processes fork from a process
-    without device state."""
+def _host_cpus():
+    """(CPUs this process may run on, CPUs the host reports, CPU model)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return usable, os.cpu_count() or usable, model
+
+
+def cpu_baseline(prob, target_s: float = 6.0, max_workers: int = 16, tau_rel: float = 1e-3):
+    """Times the FP64 oracle on this host: one core on a bounded block of
+    sub-cubes (iteration 0, uniform grid, histogram on), then one V-Sample pass
+    over all sub-cubes split into one block per worker process, and a whole
+    run to tau_rel relative error in the same way (each iteration's blocks
+    merged in block order, then the oracle's own weighting and bin adjustment
+    and the convergence test of the library).  Workers: the CPUs this process
+    may use, at most max_workers (the share of a host that one GPU's job gets).
+    Runs before the GPU is touched, so the workers fork from a process without
+    device state."""
     import multiprocessing as mp
 
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
 
-    g, m, p = O.shape(prob["dim"], prob["maxcalls"])
+    d, nb = prob["dim"], prob["nbins"]
+    g, m, p = O.shape(d, prob["maxcalls"])
+    grid0 = O.init_grid(d, nb)
     n = min(m, 20_000)
-    dt = _oracle_pass((prob, 0, n))
+    dt = _oracle_block((prob, 0, grid0, 0, n, True))[3]
     n1 = int(min(m, max(n, n * target_s / max(dt, 1e-6))))
-    dt1 = _oracle_pass((prob, 0, n1))
-    workers = max(1, min(os.cpu_count() or 1, max_workers))
-    per = max(1, min(n1, m // workers))
-    jobs = [(prob, k * per, (k + 1) * per) for k in range(workers)]
+    dt1 = _oracle_block((prob, 0, grid0, 0, n1, True))[3]
+    usable, reported, model = _host_cpus()
+    workers = max(1, min(usable, max_workers))
+    cuts = [m * k // workers for k in range(workers + 1)]
+
+    def one_pass(pool, it, grid, hist):
+        jobs = [(prob, it, grid, cuts[k], cuts[k + 1], hist) for k in range(workers)]
+        parts = pool.map(_oracle_block, jobs)
+        I = math.fsum(r[0] for r in parts)
+        V = math.fsum(r[1] for r in parts)
+        H = None
+        if hist:
+            H = np.zeros(d * nb)
+            for r in parts:
+                H = H + r[2]
+        return I, V, H
+
     with mp.get_context("fork").Pool(workers) as pool:
         t = time.perf_counter()
-        pool.map(_oracle_pass, jobs)
+        one_pass(pool, 0, grid0, True)
         wall = time.perf_counter() - t
-    return {"value": workers * per * p / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
-            "sample": f"V-Sample passes of iteration 0 (uniform grid, histogram on): {workers} processes, "
-                      f"each over {per} of the {m} sub-cubes ({workers * per * p} samples, {wall:.1f} s "
-                      f"wall); one core alone: {n1 * p} samples in {dt1:.1f} s",
-            "single_core": n1 * p / dt1}
+        # time to tau_rel: the oracle's steps of Alg. 2, each pass spread over the workers
+        run = dict(prob, tau_rel=tau_rel)
+        t = time.perf_counter()
+        grid, Is, Vs, conv = grid0, [], [], False
+        for it in range(run["itmax"]):
+            adjust = it < run["ita"]
+            I, V, H = one_pass(pool, it, grid, adjust)
+            Is.append(I)
+            Vs.append(V)
+            est, err, chi2 = O.weighted(Is, Vs)
+            if adjust:
+                grid = O.refine(d, nb, run["alpha"], H, grid)
+            if len(Is) >= 2 and err <= tau_rel * abs(est) and chi2 <= 5.0:
+                conv = True
+                break
+        t_target = time.perf_counter() - t
+    return {"value": m * p / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"one FP64 V-Sample pass of iteration 0 over all {m} sub-cubes ({m * p} samples, "
+                      f"uniform grid, histogram on) split into {workers} blocks on {workers} processes: "
+                      f"{wall:.2f} s wall; one core alone: {n1 * p} samples in {dt1:.1f} s",
+            "single_core": n1 * p / dt1,
+            "host": {"cpus_usable": usable, "cpus_reported": reported, "cpu_model": model},
+            "time_to_1e-3": {"ms": t_target * 1e3, "iterations": len(Is), "converged": conv,
+                             "estimate": est, "rel_error": err / abs(est) if est else None}}
 
 
 def _base_line(args, name, value, ms_per_step, dtype, config):
@@ -320,6 +399,75 @@ def bench_serve(args, M, W, torch):
     print(json.dumps(line))
 
 
+def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profiled_here):
+    """K full runs of one problem in one precision on a prepared workspace
+    (inputs resident), the sampling kernel's HIP-event time and roofline, and
+    the wall time of one run to a 1e-3 relative error (after one untimed run)."""
+    p = dict(prob, precision=precision)
+    bp = M.BoundProblem(p, args.blocks, args.threads)
+    ws = M.Workspace(bp)
+    M.prepare(p, ws, bp=bp)
+
+    def run(seed, **kw):
+        p["seed"] = bp.s.seed = seed
+        return M.integrate(p, ws=ws, bp=bp, prepared=True, **kw)
+
+    for w in range(warmup):
+        run(1000 + w)
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        res.append(run(1 + k, timing=True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gmp = M.shape(p["dim"], p["maxcalls"])
+    calls_per_iter = gmp[1] * gmp[2]
+    launches = sum(r.iterations for r in res)
+    avg_launch_s = sum(r.sample_ms for r in res) / launches / 1e3
+    fp32 = precision == "fp32"
+    ops = ops_per_sample(p, gmp, adjust=p["ita"] > 0, fp32=fp32)
+    achieved = ops * calls_per_iter / avg_launch_s
+    r0 = res[0]
+    prof = (profiled(precision) if profiled_here else None) or {}
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": prof.get("traffic"),
+            "kernel": "vsample_kernel" + (" (FP32-eval)" if fp32 else ""),
+            "avg_launch_ms": avg_launch_s * 1e3, "ops_per_sample": ops,
+            "launch": {"blocks": r0.blocks, "threads": r0.threads, "lds_bytes": r0.lds_bytes}}
+    if "valu_insts_per_sample" in prof:
+        # the compiled kernel's own count (rocprofv3 SQ_INSTS_VALU) at this launch time
+        roof["measured"] = {
+            "valu_insts_per_sample": prof["valu_insts_per_sample"],
+            "valu_issue_ratio": prof["valu_issue_ratio"],
+            "valu_lane_insts_per_s": prof["valu_insts_per_sample"] * calls_per_iter / avg_launch_s / 1e12,
+            "frac_of_issue_peak": prof["valu_insts_per_sample"] * calls_per_iter / avg_launch_s
+                                  / VALU_PEAK_OPS}
+
+    # time to 1e-3 relative error, on a workspace of its own
+    pt = dict(p, tau_rel=1e-3, seed=77)
+    bpt = M.BoundProblem(pt, args.blocks, args.threads)
+    wst = M.Workspace(bpt)
+    M.prepare(pt, wst, bp=bpt)
+    M.integrate(pt, ws=wst, bp=bpt, prepared=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rt = M.integrate(pt, ws=wst, bp=bpt, prepared=True)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t
+    return {"value": sum(r.calls for r in res) / elapsed, "unit": "samples/s",
+            "ms_per_step": elapsed / steps * 1e3, "calls_per_iter": calls_per_iter,
+            "kernel_samples_per_s": calls_per_iter / avg_launch_s,
+            "finalize_ms_per_iter": sum(r.finalize_ms for r in res) / launches,
+            "roofline": roof,
+            "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
+                             "estimate": rt.estimate,
+                             "rel_error": rt.error / abs(rt.estimate) if rt.estimate else None,
+                             "chi2_dof": rt.chi2_dof,
+                             "true_rel_error": abs(rt.estimate - exact) / abs(exact)},
+            "first": r0, "first_estimate": (r0.estimate, r0.error)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +475,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tables", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-corner8", action="store_true",
+                    help="tables workload: skip the d = 8 corner-peak entry")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
@@ -375,131 +525,62 @@ def main():
     if args.workload == "serve":
         return bench_serve(args, M, W, torch)
     name, make = WORKLOADS[args.workload]
-    on_tables = args.workload == "tables" and not args.one_d  # where the traffic profile was taken
     prob = make(W, 1)
     if args.one_d:
         prob["one_d"] = True
         name += "_1d"
-    bp = M.BoundProblem(prob, args.blocks, args.threads)
-    ws = M.Workspace(bp)
-    M.prepare(prob, ws, bp=bp)
-    gmp = M.shape(prob["dim"], prob["maxcalls"])
-    calls_per_iter = gmp[1] * gmp[2]
+    # where the profile summary (traffic, measured VALU figures) was taken
+    on_tables = args.workload == "tables" and not args.one_d
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import closed_forms as CF
-    exact = CF.exact(prob)
 
-    def step(seed):
-        prob["seed"] = seed
-        bp.s.seed = seed
-        return M.integrate(prob, ws=ws, bp=bp, timing=True, prepared=True)
-
-    for w in range(args.warmup):
-        step(1000 + w)
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        results.append(step(1 + k))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    calls = sum(r.calls for r in results)
-    launches = sum(r.iterations for r in results)
-    sample_ms = sum(r.sample_ms for r in results)
-    fin_ms = sum(r.finalize_ms for r in results)
-    avg_launch_s = sample_ms / launches / 1e3
-    ops = ops_per_sample(prob, gmp, adjust=prob["ita"] > 0) * calls_per_iter
-    achieved = ops / avg_launch_s
-    r0 = results[0]
-
-    def time_to_target(precision):
-        """Wall time of one run to a 1e-3 relative error, after one untimed run."""
-        pt = dict(prob, tau_rel=1e-3, precision=precision, seed=77)
-        bpt = M.BoundProblem(pt, args.blocks, args.threads)
-        wst = M.Workspace(bpt)
-        M.prepare(pt, wst, bp=bpt)
-        M.integrate(pt, ws=wst, bp=bpt, prepared=True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = M.integrate(pt, ws=wst, bp=bpt, prepared=True)
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t
-
-    rt, tt = time_to_target("fp64")
-
-    # the FP32-evaluation path on the same workload: throughput, time to 1e-3,
-    # and its distance from the FP64 run with the same seed
-    p32 = dict(prob, precision="fp32")
-    bp32 = M.BoundProblem(p32, args.blocks, args.threads)
-    ws32 = M.Workspace(bp32)
-    M.prepare(p32, ws32, bp=bp32)
-    for w in range(args.warmup):
-        p32["seed"] = bp32.s.seed = 1000 + w
-        M.integrate(p32, ws=ws32, bp=bp32, prepared=True)
-    torch.cuda.synchronize()
-    res32 = []
-    t2 = time.perf_counter()
-    for k in range(args.steps):
-        p32["seed"] = bp32.s.seed = 1 + k
-        res32.append(M.integrate(p32, ws=ws32, bp=bp32, timing=True, prepared=True))
-    torch.cuda.synchronize()
-    el32 = time.perf_counter() - t2
-    rt32, tt32 = time_to_target("fp32")
-    k32 = sum(r.sample_ms for r in res32) / sum(r.iterations for r in res32) / 1e3
-    ops32 = ops_per_sample(prob, gmp, adjust=prob["ita"] > 0, fp32=True) * calls_per_iter
-    fp32_eval = {
-        "value": sum(r.calls for r in res32) / el32, "unit": "samples/s",
-        "ms_per_step": el32 / args.steps * 1e3, "kernel_samples_per_s": calls_per_iter / k32,
-        "avg_launch_ms": k32 * 1e3,
-        "roofline": {"bound": "alu", "achieved": ops32 / k32 / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": ops32 / k32 / VALU_PEAK_OPS,
-                     "traffic": profiled_traffic("fp32") if on_tables else None,
-                     "kernel": "vsample_kernel (FP32-eval)",
-                     "ops_per_sample": ops32 / calls_per_iter},
-        "time_to_1e-3": {"ms": tt32 * 1e3, "iterations": rt32.iterations,
-                         "converged": rt32.converged, "estimate": rt32.estimate,
-                         "rel_error": rt32.error / abs(rt32.estimate),
-                         "true_rel_error": abs(rt32.estimate - exact) / abs(exact)},
-        "vs_fp64_same_seed": {
-            "rel_diff": (res32[0].estimate - results[0].estimate) / abs(results[0].estimate),
-            "in_sigma": (res32[0].estimate - results[0].estimate)
-                        / math.hypot(res32[0].error, results[0].error)},
-    }
-
+    m64 = measure_single(args, M, torch, prob, "fp64", args.steps, args.warmup, CF.exact(prob),
+                         on_tables)
+    m32 = measure_single(args, M, torch, prob, "fp32", args.steps, args.warmup, CF.exact(prob),
+                         on_tables)
+    r0 = m64.pop("first")
+    m32.pop("first")
+    first32 = m32.pop("first_estimate")
+    m64.pop("first_estimate")
+    m32["vs_fp64_same_seed"] = {
+        "rel_diff": (first32[0] - r0.estimate) / abs(r0.estimate),
+        "in_sigma": (first32[0] - r0.estimate) / math.hypot(first32[1], r0.error)}
     line = {
         "metric": "integrand samples/sec/GPU",
-        "value": calls / elapsed,
+        "value": m64.pop("value"),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": m64.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": name, "dim": prob["dim"], "maxcalls": prob["maxcalls"],
-                   "calls_per_iter": calls_per_iter, "nbins": prob["nbins"],
+                   "calls_per_iter": m64["calls_per_iter"], "nbins": prob["nbins"],
                    "itmax": prob["itmax"], "alpha": prob["alpha"],
                    "step": "one full m-Cubes run (mc_integrate_prepared, inputs resident)"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": profiled_traffic("fp64") if on_tables else None,
-                     "kernel": "vsample_kernel", "avg_launch_ms": avg_launch_s * 1e3,
-                     "ops_per_sample": ops / calls_per_iter,
-                     "launch": {"blocks": r0.blocks, "threads": r0.threads,
-                                "lds_bytes": r0.lds_bytes}},
-        "kernel_samples_per_s": calls_per_iter / avg_launch_s,
-        "finalize_ms_per_iter": fin_ms / launches,
-        "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
-                         "estimate": rt.estimate, "rel_error": rt.error / abs(rt.estimate),
-                         "true_rel_error": abs(rt.estimate - exact) / abs(exact)},
-        "estimate": {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof,
-                     "exact": exact},
-        "fp32_eval": fp32_eval,
     }
+    line.update(m64)
+    line["estimate"] = {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof,
+                        "exact": CF.exact(prob)}
+    line["fp32_eval"] = m32
+    if args.workload == "tables" and not args.no_corner8:
+        # the largest single-GPU configuration beside it: d = 8 corner peak at
+        # 1e9 samples per iteration, 20 iterations, in both precisions
+        c8 = W.config_corner8(seed=1)
+        k = max(1, min(args.steps, 3))
+        sub = {}
+        for prec in ("fp64", "fp32"):
+            r = measure_single(args, M, torch, c8, prec, k, 1, CF.exact(c8), False)
+            r.pop("first")
+            r.pop("first_estimate")
+            sub["fp64" if prec == "fp64" else "fp32_eval"] = r
+        sub["config"] = {"dim": 8, "maxcalls": c8["maxcalls"], "calls_per_iter": sub["fp64"]["calls_per_iter"],
+                         "nbins": c8["nbins"], "itmax": c8["itmax"], "steps": k}
+        line["corner_peak_d8_1e9"] = sub
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line))

@@ -133,6 +133,15 @@ mc_status mc_shape(int32_t dim, int64_t maxcalls, int64_t *g, int64_t *m, int64_
  * MC_EINVAL for an invalid problem, MC_EDEVICE if no device is usable. */
 mc_status mc_workspace_bytes(const mc_problem *prob, size_t *bytes);
 
+/* The sampling kernel's launch for the problem on the current device:
+ * workgroups, threads per workgroup and bytes of LDS per workgroup of a
+ * V-Sample pass (adjust != 0) or a V-Sample-No-Adjust pass (adjust == 0), as
+ * mc_integrate and mc_sample_iteration launch it.  Host query; no kernel
+ * runs.  MC_EINVAL for an invalid problem or a NULL output, MC_EDEVICE
+ * without a usable device. */
+mc_status mc_launch_shape(const mc_problem *prob, int32_t adjust, int32_t *blocks, int32_t *threads,
+                          int32_t *lds_bytes);
+
 /* Copies the problem's parameters and tables into the workspace and prepares
  * it for mc_sample_iteration().  mc_integrate() does this itself. */
 mc_status mc_prepare(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream);

@@ -207,10 +207,13 @@ hipError_t pass_stage(size_t bytes, char **out) {
     return hipSuccess;
 }
 
+// pinned: stage the grid and the results through page-locked memory (direct
+// DMA; allocated on first use); otherwise copy from and to the caller's
+// pageable buffers, which allocates nothing.
 mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t stream,
                    uint32_t iter, bool adjust, const double *h_grid, double *out_host,
                    double *trace, int64_t t0, int64_t t1, Events *ev, double *ms_sample,
-                   double *ms_fin, int spin_us = 0) {
+                   double *ms_fin, int spin_us = 0, bool pinned = true) {
     const int d = pr->dim, nb = pr->nbins;
     const int blocks = adjust ? G.blocks_adj : G.blocks_noadj;
     const size_t lds = adjust ? G.lds_adj : G.lds_noadj;
@@ -222,10 +225,14 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     const size_t grid_bytes = sizeof(double) * d * (nb + 1);
     const size_t nout = 4 + (adjust ? (size_t)d * nb : 0);
     char *stage = nullptr;
-    HIP_TRY(pass_stage(align_up(grid_bytes) + sizeof(double) * nout, &stage));
-    std::memcpy(stage, h_grid, grid_bytes);
-    double *out_stage = reinterpret_cast<double *>(stage + align_up(grid_bytes));
-    HIP_TRY(hipMemcpyAsync(ws + G.off_grid, stage, grid_bytes, hipMemcpyHostToDevice, stream));
+    double *out_stage = out_host;
+    if (pinned) {
+        HIP_TRY(pass_stage(align_up(grid_bytes) + sizeof(double) * nout, &stage));
+        std::memcpy(stage, h_grid, grid_bytes);
+        out_stage = reinterpret_cast<double *>(stage + align_up(grid_bytes));
+    }
+    HIP_TRY(hipMemcpyAsync(ws + G.off_grid, pinned ? stage : static_cast<const void *>(h_grid),
+                           grid_bytes, hipMemcpyHostToDevice, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[0], stream));
     HIP_TRY(allow_lds(sample_kernel(pr->integrand, d, trace != nullptr, is_fp32(pr)), lds));
     HIP_TRY(launch_sample(pr->integrand, d, blocks, G.threads, lds, stream, a));
@@ -237,7 +244,7 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     if (adjust && d > 1 && !pr->one_d) AxisPool::get().prime(spin_us);
     HIP_TRY(hipMemcpyAsync(out_stage, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    std::memcpy(out_host, out_stage, sizeof(double) * nout);
+    if (pinned) std::memcpy(out_host, out_stage, sizeof(double) * nout);
     if (ev) {
         float a_ms = 0.f, b_ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&a_ms, ev->e[0], ev->e[1]));
@@ -311,6 +318,18 @@ mc_status mc_workspace_bytes(const mc_problem *prob, size_t *bytes) {
     return MC_OK;
 }
 
+mc_status mc_launch_shape(const mc_problem *prob, int32_t adjust, int32_t *blocks, int32_t *threads,
+                          int32_t *lds_bytes) {
+    if (!blocks || !threads || !lds_bytes) return MC_EINVAL;
+    Geometry G;
+    mc_status st = geometry(prob, &G);
+    if (st != MC_OK) return st;
+    *blocks = adjust ? G.blocks_adj : G.blocks_noadj;
+    *threads = G.threads;
+    *lds_bytes = (int32_t)(adjust ? G.lds_adj : G.lds_noadj);
+    return MC_OK;
+}
+
 mc_status mc_prepare(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream) {
     Geometry G;
     mc_status st = geometry(prob, &G);
@@ -380,7 +399,8 @@ namespace {
 // Alg. 2 on a workspace; upload: copy the constants and tables first
 // (otherwise a previous mc_prepare() of the same problem left them there).
 mc_status integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream, bool upload,
-                    mc_result *out, double *h_iters, double *h_grid, mc_timing *timing) {
+                    mc_result *out, double *h_iters, double *h_grid, mc_timing *timing,
+                    bool pinned = true) {
     if (!out) return MC_EINVAL;
     Geometry G;
     mc_status st = geometry(prob, &G);
@@ -406,7 +426,7 @@ mc_status integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *s
         const bool adjust = it < prob->ita;
         const auto pass_start = std::chrono::steady_clock::now();
         st = run_pass(prob, G, ws, s, (uint32_t)it, adjust, grid.data(), buf.data(), nullptr, 0, 0,
-                      timing ? &ev : nullptr, &ms_s, &ms_f, spin_us);
+                      timing ? &ev : nullptr, &ms_s, &ms_f, spin_us, pinned);
         if (st != MC_OK) return st;
         const double pass_us = std::chrono::duration<double, std::micro>(
                                    std::chrono::steady_clock::now() - pass_start).count();

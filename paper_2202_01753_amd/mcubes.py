@@ -21,7 +21,7 @@ LIBRARY = os.path.join(PKG, "libmcubes.so")
 OK, EINVAL, EWORKSPACE, ENONFINITE, EDEVICE = 0, 1, 2, 3, 4
 INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
-EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_prepare",
+EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_launch_shape", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
            "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared",
            "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
@@ -95,6 +95,7 @@ def lib() -> C.CDLL:
             "mc_status_string": ([C.c_int32], C.c_char_p),
             "mc_shape": ([C.c_int32, C.c_int64] + [C.POINTER(C.c_int64)] * 3, C.c_int32),
             "mc_workspace_bytes": ([P, C.POINTER(C.c_size_t)], C.c_int32),
+            "mc_launch_shape": ([P, C.c_int32] + [C.POINTER(C.c_int32)] * 3, C.c_int32),
             "mc_prepare": ([P, vp, sz, vp], C.c_int32),
             "mc_sample_iteration": ([P, C.c_uint32, C.c_int32, dp, vp, sz, vp, dp, dp, vp, sz,
                                      C.c_int64, C.c_int64], C.c_int32),
@@ -181,6 +182,14 @@ def workspace_bytes(bp: BoundProblem) -> int:
     n = C.c_size_t()
     _check(lib().mc_workspace_bytes(bp.ref, C.byref(n)), "mc_workspace_bytes")
     return n.value
+
+
+def launch_shape(bp: BoundProblem, adjust: bool = True):
+    """(workgroups, threads per workgroup, LDS bytes) of the sampling launch."""
+    b, t, l = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().mc_launch_shape(bp.ref, 1 if adjust else 0, C.byref(b), C.byref(t), C.byref(l)),
+           "mc_launch_shape")
+    return b.value, t.value, l.value
 
 
 def refine_grid(dim: int, nbins: int, alpha: float, hist, grid):

@@ -11,6 +11,7 @@ from paper_2202_01753_amd import workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 _spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
 B = importlib.util.module_from_spec(_spec)
+sys.modules["bench_host"] = B  # worker processes look the module up by name
 _spec.loader.exec_module(B)
 
 
@@ -65,3 +66,14 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_baseline_runs_the_oracle_on_the_host():
+    """The CPU leg on the small configuration: a pass over all sub-cubes split
+    across worker processes, a run to 1e-3, and the host's CPUs recorded."""
+    prob = W.config_small(seed=1)
+    r = B.cpu_baseline(prob, target_s=0.1, max_workers=4)
+    assert r["kind"] == "oracle" and r["value"] > 0 and 1 <= r["cores"] <= 4
+    assert r["host"]["cpus_usable"] >= 1 and r["host"]["cpu_model"]
+    t = r["time_to_1e-3"]
+    assert t["converged"] and t["iterations"] >= 2 and t["rel_error"] <= 1e-3

@@ -108,27 +108,64 @@ def _compare_totals(gpu, ref, scale, label="", tol=TOL):
             f"{label}: histogram"
 
 
+def _positive_scale(ref):
+    """sum_t |I_t| for an integrand that is never negative (all the closed forms
+    and the tables here): the pass total itself."""
+    return abs(ref["I"])
+
+
+def _refined_grids_agree(prob, gpu_hist, ref_hist, grid, gpu_grid, tol):
+    """The grid the run goes on with (refined by the library from the GPU
+    histogram) against the oracle's own refinement of the oracle's histogram.
+    Bit-identical when the two histograms are.  When every bin agrees within
+    tol relative, within 100 tol absolute: 1e-12 relative perturbations of
+    these histograms move no boundary by more than 3e-13 (measured on the
+    CPU).  Lepage's compression weighs a bin by about 1/ln(S/s_i), so a bin
+    that is exactly 0 on one side and a tiny subnormal on the other (float
+    expf of ocml and glibc differ there) can move boundaries by far more; that
+    case arises only for FP32 exponentials and is not compared."""
+    d, nb, alpha = prob["dim"], prob["nbins"], prob["alpha"]
+    refine = O.refine_1d if prob.get("one_d") else O.refine
+    want = refine(d, nb, alpha, ref_hist, grid)
+    if np.array_equal(gpu_hist, ref_hist):
+        assert np.array_equal(gpu_grid, want), "refined grids differ on equal histograms"
+    elif np.all(np.abs(gpu_hist - ref_hist) <= tol * np.abs(ref_hist)):
+        assert np.abs(gpu_grid - want).max() <= 100 * tol, "refined grids differ"
+    else:
+        assert _fp32(prob) and not _exact_f(prob), "histograms differ beyond rounding"
+
+
 def _lockstep(prob, iters=None, threads=0, blocks=0):
+    """Every iteration: the traced pass (same kernel template, tracing
+    instantiation) against the oracle sample by sample, then the production
+    pass that the benchmark times, untraced, against the same oracle pass;
+    the run goes on with the grid refined from the production pass."""
     d, nb = prob["dim"], prob["nbins"]
     s = M.Sampler(prob, blocks=blocks, threads=threads)
     grid = O.init_grid(d, nb)
     iters = prob["itmax"] if iters is None else iters
+    tol = _tol(prob)
     for it in range(iters):
         adjust = it < prob["ita"]
         gpu = s.sample(it, grid, adjust, trace_range=(0, s.m))
         gpu["nbins"] = nb
         ref = O.vsample(prob, it, grid, hist=adjust, trace=True)
         scale = _compare_records(prob, gpu, ref, f"iter {it}")
-        _compare_totals(gpu, ref, scale, f"iter {it}", _tol(prob))
+        _compare_totals(gpu, ref, scale, f"iter {it}", tol)
+        prod = s.sample(it, grid, adjust)
+        prod["nbins"] = nb
+        _compare_totals(prod, ref, scale, f"iter {it} (production kernel)", tol)
         if adjust and prob.get("one_d"):
-            a = M.refine_grid_1d(d, nb, prob["alpha"], gpu["hist"], grid)
-            b = O.refine_1d(d, nb, prob["alpha"], gpu["hist"], grid)
+            a = M.refine_grid_1d(d, nb, prob["alpha"], prod["hist"], grid)
+            b = O.refine_1d(d, nb, prob["alpha"], prod["hist"], grid)
             assert np.array_equal(a, b), f"iter {it}: refined grids differ"
+            _refined_grids_agree(prob, prod["hist"], ref["hist"], grid, a, tol)
             grid = a
         elif adjust:
-            a = M.refine_grid(d, nb, prob["alpha"], gpu["hist"], grid)
-            b = O.refine(d, nb, prob["alpha"], gpu["hist"], grid)
+            a = M.refine_grid(d, nb, prob["alpha"], prod["hist"], grid)
+            b = O.refine(d, nb, prob["alpha"], prod["hist"], grid)
             assert np.array_equal(a, b), f"iter {it}: refined grids differ"
+            _refined_grids_agree(prob, prod["hist"], ref["hist"], grid, a, tol)
             grid = a
     return grid
 
@@ -429,3 +466,152 @@ def test_one_d_integrate_matches_oracle():
     assert g.estimate == pytest.approx(o["estimate"], rel=1e-11)
     assert np.array_equal(g.grid.reshape(5, -1)[0], g.grid.reshape(5, -1)[4])
     assert abs(g.estimate - CF.exact(prob)) < 5 * g.error
+
+
+# ---------------------------------------------------------------- production kernels at benchmark shapes
+#
+# The kernels the benchmark times (not the tracing instantiations), at the
+# launch shape the library picks, on problems large enough that every lane
+# strides over at least ten sub-cubes (so the grid-stride loop and its digit
+# odometer run many times per lane), against the oracle's whole pass:
+# estimate, variance and the full d x nb histogram.  The integrands are
+# positive, so sum_t |I_t| is the pass total.
+
+def _random_grid(d, nb, seed):
+    rng = np.random.default_rng(seed)
+    return np.concatenate([np.concatenate([[0.0], np.sort(rng.random(nb - 1)), [1.0]])
+                           for _ in range(d)])
+
+
+def _gauss_quantile_grid(prob):
+    """Per axis, bins of equal mass of the axis's Gaussian factor exp(-((x-c)/w)^2)
+    (a grid VEGAS would adapt towards), so that most samples of a narrow peak
+    give non-zero values."""
+    from scipy.stats import norm
+    d, nb = prob["dim"], prob["nbins"]
+    c, w = prob["params"][:d], prob["params"][d:]
+    rows = []
+    for j in range(d):
+        lo, hi = norm.cdf(-c[j] / (w[j] / math.sqrt(2))), norm.cdf((1 - c[j]) / (w[j] / math.sqrt(2)))
+        q = c[j] + w[j] / math.sqrt(2) * norm.ppf(lo + (hi - lo) * np.arange(1, nb) / nb)
+        q = np.maximum.accumulate(np.clip(q, 0.0, 1.0))
+        rows.append(np.concatenate([[0.0], q, [1.0]]))
+    return np.concatenate(rows)
+
+
+def _production_passes(prob, grids, noadjust=True):
+    d, nb = prob["dim"], prob["nbins"]
+    s = M.Sampler(prob)
+    blocks, threads, _ = M.launch_shape(s.bp, adjust=True)
+    assert s.m >= 10 * blocks * threads, (s.m, blocks, threads)
+    tol = _tol(prob)
+    for it, grid in enumerate(grids):
+        label = f"{prob['integrand']} d={d} {prob.get('precision', 'fp64')} iter {it}"
+        print(label, "blocks", blocks, "threads", threads, "cubes", s.m, flush=True)
+        gpu = s.sample(it, grid, True)
+        gpu["nbins"] = nb
+        ref = O.vsample(prob, it, grid, hist=True)
+        _compare_totals(gpu, ref, _positive_scale(ref), label, tol)
+        a = M.refine_grid(d, nb, prob["alpha"], gpu["hist"], grid)
+        _refined_grids_agree(prob, gpu["hist"], ref["hist"], grid, a, tol)
+    if noadjust:
+        it = len(grids)
+        nblocks, nthreads, _ = M.launch_shape(s.bp, adjust=False)
+        assert s.m >= 10 * nblocks * nthreads
+        gpu = s.sample(it, grids[-1], False)
+        ref = O.vsample(prob, it, grids[-1], hist=False)
+        _compare_totals(gpu, ref, _positive_scale(ref), f"no-adjust iter {it}", tol)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_production_tables_d6(precision):
+    prob = W.config_tables(seed=4, maxcalls=10_000_000, itmax=3, precision=precision)
+    _production_passes(prob, [O.init_grid(6, 500), _random_grid(6, 500, 3)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_production_corner_peak_d8(precision):
+    prob = W.config_corner8(seed=4, maxcalls=2 * 8**8, itmax=2, precision=precision)
+    _production_passes(prob, [_random_grid(8, 500, 5)], noadjust=precision == "fp32")
+
+
+@pytest.mark.parametrize("precision,g", [("fp64", 7), ("fp32", 8)])
+def test_production_narrow_gaussian_d8(precision, g):
+    """w = 0.01: on equal bins almost every sample is exp(-(hundreds)); on the
+    Gaussian-quantile grid most are of order one.  (The FP32 kernel runs six
+    times as many lanes, hence the larger lattice.)"""
+    prob = W.config_gauss8(seed=4, maxcalls=2 * g**8, itmax=3, precision=precision)
+    _production_passes(prob, [O.init_grid(8, 500), _gauss_quantile_grid(prob)])
+
+
+def test_narrow_gaussian_d8_free_running_matches_oracle():
+    """The whole run at 1e7 samples per iteration, five iterations: each
+    iteration's estimate as the oracle's (which adapts the same way from the
+    same samples), and neither claims convergence: the estimates climb by tens
+    of orders of magnitude as the grid creeps towards a peak of width 0.01."""
+    prob = W.config_gauss8(seed=2, maxcalls=10_000_000, itmax=5, tau_rel=1e-3)
+    g = M.integrate(prob)
+    o = O.integrate(prob)
+    assert g.iterations == o["iterations"] == 5
+    assert not g.converged and not o["converged"]
+    assert np.allclose(g.it_I, o["it_I"], rtol=1e-11, atol=0)
+    assert np.allclose(g.it_var, o["it_var"], rtol=1e-10, atol=0)
+    assert g.estimate == pytest.approx(o["estimate"], rel=1e-11)
+    assert g.error >= 0.5 * abs(g.estimate)
+
+
+def test_fp32_underflow_is_not_an_exact_zero():
+    """FP32 evaluation of the w = 0.01 Gaussian at 1e6 samples: every expf
+    underflows, so every iteration is 0 with variance 0.  The result is 0 with
+    an infinite error and not converged, as in the oracle (before, such
+    iterations counted as exact and the run stopped at 0 +- 0)."""
+    prob = W.config_gauss8(seed=2, maxcalls=1_000_000, itmax=4, tau_rel=1e-3, precision="fp32")
+    g = M.integrate(prob)
+    o = O.integrate(prob)
+    assert (g.estimate, g.error, g.iterations, g.converged) == (0.0, math.inf, 4, False)
+    assert (o["estimate"], o["error"], o["iterations"], o["converged"]) == (0.0, math.inf, 4, False)
+
+
+def test_fp32_jacobian_overflow_is_reported():
+    """d = 12 on (0, 1e4)^12: the float Jacobian overflows; the FP32 pass must
+    report a non-finite value (the FP64 pass of the same problem is finite)."""
+    d = 12
+    prob = W.symmetric_corner(d, a=1.0, maxcalls=2**13, nbins=8, itmax=2, lo=np.zeros(d),
+                              hi=np.full(d, 1e4))
+    M.integrate(prob)
+    with pytest.raises(M.MCubesError) as e:
+        M.integrate(dict(prob, precision="fp32"))
+    assert e.value.code == M.ENONFINITE
+
+
+def test_resume_from_saved_state(tmp_path):
+    """Five iterations through the step-level calls, the state (grid and
+    per-iteration results) saved and loaded, five more: the 10-iteration
+    mc_integrate with the same seed, to the rounding of the histogram sums."""
+    prob = W.config_tables(seed=6, maxcalls=1_000_000, itmax=10, ita=8)
+    whole = M.integrate(prob)
+    s = M.Sampler(prob)
+    d, nb = prob["dim"], prob["nbins"]
+
+    def run(it0, it1, grid, Is, Vs):
+        for it in range(it0, it1):
+            adjust = it < prob["ita"]
+            r = s.sample(it, grid, adjust)
+            Is.append(r["I"])
+            Vs.append(r["var"])
+            if adjust:
+                grid = M.refine_grid(d, nb, prob["alpha"], r["hist"], grid)
+        return grid
+
+    Is, Vs = [], []
+    grid = run(0, 5, M.init_grid(d, nb), Is, Vs)
+    np.savez(tmp_path / "state.npz", grid=grid, I=np.array(Is), V=np.array(Vs))
+    st = np.load(tmp_path / "state.npz")
+    Is, Vs = list(st["I"]), list(st["V"])
+    grid = run(5, 10, st["grid"], Is, Vs)
+    est, err, chi2 = M.weighted_estimate(Is, Vs)
+    assert np.allclose(Is, whole.it_I, rtol=1e-12, atol=0)
+    assert np.allclose(Vs, whole.it_var, rtol=1e-11, atol=0)
+    assert est == pytest.approx(whole.estimate, rel=1e-12)
+    assert err == pytest.approx(whole.error, rel=1e-11)
+    assert np.abs(grid - whole.grid).max() <= 1e-10
