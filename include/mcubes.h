@@ -213,6 +213,22 @@ mc_status mc_integrate_prepared(const mc_problem *prob, void *d_ws, size_t ws_by
                                 mc_result *out, double *h_iters, double *h_grid,
                                 mc_timing *timing);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that must not allocate): mc_integrate() without a
+ * workspace.  The library runs the problem in a device scratch array of
+ * MC_NOALLOC_SCRATCH_BYTES that it holds on every GPU it is loaded on until
+ * the process ends; nothing is allocated, neither on the device nor as
+ * page-locked host memory (the per-iteration copies go through the caller's
+ * pageable memory).  Arguments, results and errors as for mc_integrate(),
+ * plus MC_EWORKSPACE when mc_workspace_bytes() of the problem exceeds the
+ * scratch size (fewer workgroups, prob->blocks, need less).  All calls on one
+ * device share its array and are serialised by the library (a call waits for
+ * the previous one to finish); the array keeps the last call's contents,
+ * which the next call overwrites before reading. */
+#define MC_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+mc_status mc_integrate_noalloc(const mc_problem *prob, void *stream, mc_result *out,
+                               double *h_iters, double *h_grid);
+
 /* ---------------------------------------------------------------- batches and serving
  *
  * Many independent integrals advanced together.  Every step runs one sampling

@@ -73,6 +73,12 @@ void weighted(int k, const double *I, const double *var, double *out);
 // tau_rel |est[0]| and est[2] (chi^2/dof) within the problem's bound.
 bool check_convergence(const mc_problem *pr, int k, const double *est);
 
+// mc_integrate on the given device buffer with the per-pass host copies made
+// from and to pageable memory: no page-locked staging is allocated (the
+// entry point that allocates nothing runs on this).
+mc_status integrate_unpinned(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                             mc_result *out, double *h_iters, double *h_grid);
+
 // A few host threads that take the axes of one bin adjustment in parallel
 // (axes are independent, so the result does not depend on the split).  The
 // jobs are short (tens of microseconds), so the driver primes the pool while

@@ -485,3 +485,14 @@ mc_status mc_integrate_prepared(const mc_problem *prob, void *d_ws, size_t ws_by
 }
 
 }  // extern "C"
+
+namespace mcubes {
+namespace host {
+
+mc_status integrate_unpinned(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *stream,
+                             mc_result *out, double *h_iters, double *h_grid) {
+    return integrate(prob, d_ws, ws_bytes, stream, true, out, h_iters, h_grid, nullptr, false);
+}
+
+}  // namespace host
+}  // namespace mcubes

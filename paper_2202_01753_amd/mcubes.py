@@ -23,7 +23,7 @@ INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 
 PRECISIONS = {"fp64": 0, "fp32": 1}
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_launch_shape", "mc_prepare",
            "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
-           "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared",
+           "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared", "mc_integrate_noalloc",
            "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
            "mc_server_set_step_budget", "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
            "mc_server_release", "mc_server_stats", "mc_server_destroy")
@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
                              C.c_int32),
             "mc_integrate_prepared": ([P, vp, sz, vp, C.POINTER(Result), dp, dp,
                                        C.POINTER(Timing)], C.c_int32),
+            "mc_integrate_noalloc": ([P, vp, C.POINTER(Result), dp, dp], C.c_int32),
             "mc_batch_workspace_bytes": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
             "mc_batch_integrate": ([P, C.c_int32, vp, sz, vp, C.POINTER(Result),
                                     C.POINTER(C.c_int32), C.POINTER(BatchStats)], C.c_int32),
@@ -295,6 +296,21 @@ def integrate(prob: dict, ws: Workspace | None = None, stream=None, blocks: int 
         out.sample_ms, out.finalize_ms = tm.sample_ms, tm.finalize_ms
         out.blocks, out.threads, out.lds_bytes = tm.blocks, tm.threads, tm.lds_bytes
     return out
+
+
+def integrate_noalloc(prob: dict, stream=None, bp: BoundProblem | None = None):
+    """mc_integrate_noalloc: the whole run in the library's device scratch array
+    (no workspace, nothing allocated by the call)."""
+    bp = bp or BoundProblem(prob)
+    d, nb, itmax = int(prob["dim"]), int(prob["nbins"]), int(prob["itmax"])
+    res = Result()
+    iters = np.zeros(2 * itmax)
+    grid = np.zeros(d * (nb + 1))
+    _check(lib().mc_integrate_noalloc(bp.ref, _stream(stream), C.byref(res), _dp(iters), _dp(grid)),
+           "mc_integrate_noalloc")
+    k = res.iterations
+    return IntegrationResult(res.estimate, res.error, res.chi2_dof, k, bool(res.converged),
+                             res.calls, iters[0:2 * k:2].copy(), iters[1:2 * k:2].copy(), grid)
 
 
 class Sampler:
