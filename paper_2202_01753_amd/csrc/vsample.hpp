@@ -298,15 +298,29 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
 template <int F, int D, bool F32>
 constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 : D <= 11);
 
+// Whether the single-integral kernel keeps each axis's lower bound in vector
+// registers for the whole launch.  The point x = lo + span xu is one fma with
+// two scalar operands otherwise, which the hardware cannot read in one
+// instruction, so every sample moved lo into a vector register first (two
+// moves per axis).  Taken for the FP64 Gaussian and table kernels of
+// d = 6..8 (5% fewer VALU instructions at d = 6 and 8, 1.5-1.7% faster),
+// which stay within the registers of four waves per SIMD; at lower d the
+// extra registers cost waves, at higher d they spill, and the d = 8
+// corner-peak kernel would pass 80 registers and lose a wave per SIMD.
+template <int F, int D, bool F32>
+constexpr bool kLowInVgpr = !F32 && (F == 1 || F == 3) && D >= 6 && D <= 8;
+
 // All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
 // contributions to the LDS histogram when collecting them, and records the
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
 // (kPairSamples for a kernel of its own; kernels that inline many cases into
-// one register allocation leave it off).  EARLY: see Integrand.
+// one register allocation leave it off).  EARLY: see Integrand.  lov: the
+// axes' lower bounds held in vector registers (kLowInVgpr), or nullptr to
+// read them with the other constants.
 template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, typename A, typename CP>
 __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
-                                          bool &bad) {
+                                          bool &bad, const real_t<F32> *lov = nullptr) {
     using R = real_t<F32>;
     constexpr bool kBatchConsts = !F32 && (F == 1 || F == 3);  // see axis_consts
     constexpr int NBLK = (D + 1) / 2;                      // blocks in the counter layout
@@ -366,7 +380,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
                 const R xu = rfma(frac, width, left);
                 const auto cj = axis_consts<kBatchConsts>(sC, j);
-                const R xj = rfma(cj[1], xu, cj[0]);
+                const R xj = rfma(cj[1], xu, lov ? lov[j] : R(cj[0]));
                 J = J * (width * cj[2]);
                 bin[j] = i;
                 fx.axis(j, xj, cj);
@@ -389,14 +403,12 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
             return Fv * a.inv;
         };
         // shifted sums in sample order
+        // (for k == 0 the deviation is exactly +0 and leaves S1 = S2 = +0)
         auto accumulate = [&](int k, double Ik) {
-            if (k == 0) {
-                I0 = Ik;
-            } else {
-                const double dev = Ik - I0;
-                S1 = S1 + dev;
-                S2 = __fma_rn(dev, dev, S2);
-            }
+            if (k == 0) I0 = Ik;
+            const double dev = Ik - I0;
+            S1 = S1 + dev;
+            S2 = __fma_rn(dev, dev, S2);
         };
         auto add_bins = [&](const int (&bin)[D], double Ik) {
             if (a.hist) {
@@ -469,7 +481,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
                 const R xu = rfma(frac, width, left);
                 const auto cj = axis_consts<kBatchConsts>(sC, j);
-                const R xj = rfma(cj[1], xu, cj[0]);
+                const R xj = rfma(cj[1], xu, lov ? lov[j] : R(cj[0]));
                 J = J * (width * cj[2]);
                 bin[j] = i;
                 fx.axis(j, xj, cj);
@@ -484,10 +496,9 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
             const double Fv = (double)f * (double)J;
             bad |= !isfinite(Fv);
             const double Ik = Fv * a.inv;
-            if (k == 0) {
-                I0 = Ik;
-            } else {
-                const double dev = Ik - I0;
+            if (k == 0) I0 = Ik;
+            {
+                const double dev = Ik - I0;  // exactly +0 for k == 0: S1, S2 stay +0
                 S1 = S1 + dev;
                 S2 = __fma_rn(dev, dev, S2);
             }
@@ -605,9 +616,18 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     digits_of<D>(t, (uint32_t)a.g, dig);
     double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
     bool bad = false;
+    // the lower bounds, copied once into vector registers (the empty asm keeps
+    // the copies there rather than reloading them as scalars)
+    real_t<F32> lov[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lov[j] = sC[kConstStride * j];
+        if constexpr (kLowInVgpr<F, D, F32>) asm volatile("" : "+v"(lov[j]));
+    }
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true>(a, v, sC, t, dig, It, vt, bad);
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true>(
+            a, v, sC, t, dig, It, vt, bad, kLowInVgpr<F, D, F32> ? lov : nullptr);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         // next sub-cube of this lane: t += stride, digit by digit
