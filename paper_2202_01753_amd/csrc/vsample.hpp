@@ -314,10 +314,13 @@ constexpr bool kLowInVgpr = !F32 && (F == 1 || F == 3) && D >= 6 && D <= 8;
 // contributions to the LDS histogram when collecting them, and records the
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
 // (kPairSamples for a kernel of its own; kernels that inline many cases into
-// one register allocation leave it off).  EARLY: see Integrand.  lov: the
-// axes' lower bounds held in vector registers (kLowInVgpr), or nullptr to
-// read them with the other constants.
-template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, typename A, typename CP>
+// one register allocation leave it off).  EARLY: see Integrand.  LOV: lov
+// holds the axes' lower bounds in vector registers (kLowInVgpr); otherwise
+// they are read with the other constants.  (A compile-time choice: a null
+// pointer tested at run time, though folded away, changed the FP32 d = 8
+// kernels' register allocation from 72 to 90.)
+template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, bool LOV = false, typename A,
+          typename CP>
 __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad, const real_t<F32> *lov = nullptr) {
@@ -380,7 +383,11 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
                 const R xu = rfma(frac, width, left);
                 const auto cj = axis_consts<kBatchConsts>(sC, j);
-                const R xj = rfma(cj[1], xu, lov ? lov[j] : R(cj[0]));
+                R xj;
+                if constexpr (LOV)
+                    xj = rfma(cj[1], xu, lov[j]);
+                else
+                    xj = rfma(cj[1], xu, cj[0]);
                 J = J * (width * cj[2]);
                 bin[j] = i;
                 fx.axis(j, xj, cj);
@@ -481,7 +488,11 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 }
                 const R xu = rfma(frac, width, left);
                 const auto cj = axis_consts<kBatchConsts>(sC, j);
-                const R xj = rfma(cj[1], xu, lov ? lov[j] : R(cj[0]));
+                R xj;
+                if constexpr (LOV)
+                    xj = rfma(cj[1], xu, lov[j]);
+                else
+                    xj = rfma(cj[1], xu, cj[0]);
                 J = J * (width * cj[2]);
                 bin[j] = i;
                 fx.axis(j, xj, cj);
@@ -619,15 +630,17 @@ __global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) 
     // the lower bounds, copied once into vector registers (the empty asm keeps
     // the copies there rather than reloading them as scalars)
     real_t<F32> lov[D];
+    if constexpr (kLowInVgpr<F, D, F32>) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        lov[j] = sC[kConstStride * j];
-        if constexpr (kLowInVgpr<F, D, F32>) asm volatile("" : "+v"(lov[j]));
+        for (int j = 0; j < D; ++j) {
+            lov[j] = sC[kConstStride * j];
+            asm volatile("" : "+v"(lov[j]));
+        }
     }
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true>(
-            a, v, sC, t, dig, It, vt, bad, kLowInVgpr<F, D, F32> ? lov : nullptr);
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true, kLowInVgpr<F, D, F32>>(
+            a, v, sC, t, dig, It, vt, bad, lov);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         // next sub-cube of this lane: t += stride, digit by digit
