@@ -237,3 +237,28 @@ def test_server_step_budget_rejects_negative():
         srv.set_step_budget(10, -1)
     srv.set_step_budget(0, 0)
     srv.close()
+
+
+def test_served_requests_match_the_oracle():
+    """Requests served with continuous batching (one arriving after two steps,
+    while the others run) against the oracle's whole run of each, not against
+    the batch engine alone: a d = 6 table integral, a d = 10 Gaussian with 500
+    bins per axis (80 KB of LDS: the wide-workgroup launch group), a corner
+    peak that converges to its target, and a d = 3 Gaussian product.  The
+    served grids are refined on the device (device pow and log), so estimates
+    agree to 1e-10 relative rather than bit for bit."""
+    probs = [
+        W.config_tables(seed=61, maxcalls=400_000, itmax=4),
+        W.gauss_product(10, 62, w_range=(0.1, 0.3), maxcalls=1_000_000, nbins=500, itmax=3, seed=63),
+        W.corner_peak(5, 64, maxcalls=200_000, nbins=100, itmax=12, tau_rel=1e-3, seed=65),
+        W.gauss_product(3, 66, maxcalls=50_000, nbins=100, itmax=6, seed=67),
+    ]
+    served, _, _ = _serve_all(probs, late=(3,))
+    for i, p in enumerate(probs):
+        print("served request", i, p["integrand"], p["dim"], p["nbins"], flush=True)
+        o = O.integrate(p)
+        r = served[i]
+        assert r["iterations"] == o["iterations"] and r["converged"] == o["converged"]
+        assert r["estimate"] == pytest.approx(o["estimate"], rel=MIX_TOL, abs=0)
+        assert r["error"] == pytest.approx(o["error"], rel=100 * MIX_TOL, abs=0)
+    assert served[2]["converged"] and served[2]["iterations"] < 12
