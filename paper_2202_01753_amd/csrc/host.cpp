@@ -4,6 +4,8 @@
 // given histogram always yields the same grid.
 #include "host.hpp"
 
+#include "estimate.hpp"
+
 #include <cmath>
 #include <cstring>
 
@@ -192,59 +194,13 @@ void refine_1d(int d, int nb, double alpha, const double *hist, double *grid) {
     for (int j = 1; j < d; ++j) std::copy(grid, grid + nb + 1, grid + (size_t)j * (nb + 1));
 }
 
-// Iterations with I = 0 and var = 0 saw no non-zero sample and carry no
-// information, so they take no part; among the others an exact iteration
-// (var = 0) decides the mean alone.
 void weighted(int k, const double *I, const double *var, double *out) {
-    int used = 0, exact = 0;
-    double exact_sum = 0.0;
-    for (int i = 0; i < k; ++i) {
-        if (var[i] == 0.0 && I[i] == 0.0) continue;
-        ++used;
-        if (var[i] == 0.0) {
-            ++exact;
-            exact_sum = exact_sum + I[i];
-        }
-    }
-    if (used == 0) {
-        out[0] = 0.0;
-        out[1] = INFINITY;
-        out[2] = NAN;
-        return;
-    }
-    if (exact) {
-        out[0] = exact_sum / (double)exact;
-        out[1] = 0.0;
-        out[2] = used > 1 ? 0.0 : NAN;
-        return;
-    }
-    double wsum = 0.0, wisum = 0.0;
-    for (int i = 0; i < k; ++i) {
-        if (var[i] == 0.0) continue;
-        const double w = 1.0 / var[i];
-        wsum = wsum + w;
-        wisum = wisum + w * I[i];
-    }
-    const double mean = wisum / wsum;
-    double chi = 0.0;
-    for (int i = 0; i < k; ++i) {
-        if (var[i] == 0.0) continue;
-        const double dv = I[i] - mean;
-        chi = chi + (dv * dv) / var[i];
-    }
-    out[0] = mean;
-    out[1] = 1.0 / std::sqrt(wsum);
-    out[2] = used > 1 ? chi / (double)(used - 1) : NAN;
+    weighted_estimate(k, I, var, out);
 }
 
 bool check_convergence(const mc_problem *pr, int k, const double *est) {
-    if (k < 2 || !(pr->tau_rel > 0.0)) return false;
-    if (!(est[1] <= pr->tau_rel * std::fabs(est[0]))) return false;
-    if (pr->chi2_max < 0.0) return true;
-    const double bound = pr->chi2_max > 0.0 ? pr->chi2_max : MC_CHI2_DOF_DEFAULT;
-    return est[2] <= bound;  // false for NaN (fewer than two informative iterations)
+    return converged_after(k, est, pr->tau_rel, pr->chi2_max);
 }
-
 
 void sample_args(const mc_problem *pr, int64_t g, int64_t m, int64_t p, uint32_t iter, bool adjust,
                  const void *consts, const double *grid, const void *tables, SampleArgs *a) {

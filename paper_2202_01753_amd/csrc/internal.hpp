@@ -74,14 +74,33 @@ hipError_t launch_clear_flag(uint32_t *flag, hipStream_t stream);
 // their bin contributions into it (zero at admission and after every bin
 // adjustment); when refine is set, the grid is adjusted on the device from
 // that histogram after the pass.
+//
+// Each integral also keeps on the device the results of all its iterations
+// (iters: I_0.. I_{itmax-1}, then var_0 .. var_{itmax-1}) and a state word:
+// the merge kernel runs Weighted-Estimates and Check-Convergence after every
+// pass and sets the state once the integral stops (converged, out of
+// iterations, or a non-finite value).  Later steps may still list it (the
+// host learns of the stop one step later); its segments then do no work.
 struct BatchItem {
     SampleArgs a;
-    double *grid;     // the integral's grid (a.grid, writable)
+    double *grid;       // the integral's grid (a.grid, writable)
     double *out;
+    double *iters;      // 2 * itmax doubles
+    uint32_t *state;    // kItemRunning until the integral stops
     double alpha;
+    double tau_rel;     // Check-Convergence: target relative error (0: never converged)
+    double chi2_max;    //   and bound on chi^2/dof (0: default, negative: unchecked)
+    int32_t itmax;
     int32_t refine;
-    int32_t pad;
 };
+
+// Item states, and the merge kernel's per-step results (kResStride doubles
+// per listed integral: I, var, non-finite flag, weighted estimate, its
+// standard deviation, chi^2/dof, state after the pass or kResSkipped, 1 if
+// converged).
+constexpr uint32_t kItemRunning = 0, kItemDone = 1, kItemFailed = 2;
+constexpr int kResStride = 8;
+constexpr double kResSkipped = -1.0;
 
 // A contiguous range of one integral's sub-cubes, processed by one workgroup.
 struct BatchSegment {
@@ -101,7 +120,7 @@ struct BatchArgs {
     const int32_t *item_first;
     double *seg_tot;          // 4 doubles per segment
     uint32_t *flags;          // per item, zero before the step
-    double *res;              // per item: I, var, flag, 0 (packed for one read-back)
+    double *res;              // per item: kResStride doubles (packed for one read-back)
     uint32_t *queue;          // this launch's segment counter
     int32_t lo, hi;           // this launch's range of order
     int32_t n_items;
@@ -115,6 +134,7 @@ struct AdmitRecord {
     char *consts;         // destination of the constants in the integral's block
     double *grid;         // destination of the d*(nb+1) starting boundaries
     double *out;          // the integral's 4 + d*nb output doubles
+    uint32_t *state;      // the integral's state word (set to kItemRunning)
     int64_t src;          // byte offset of the constants in the upload (4-byte aligned)
     int32_t const_words;  // 4-byte words of constants
     int32_t dim, nb, pad;
@@ -128,7 +148,9 @@ hipError_t launch_admit(const AdmitRecord *recs, int n, const char *upload, hipS
 hipError_t launch_batch(bool fp32, bool tables, int blocks, int threads, size_t lds_bytes,
                         hipStream_t stream, const BatchArgs &args);
 const void *batch_kernel(bool fp32, bool tables);
-// Merges every integral's segment totals in order into its out and res and clears its flag.
+// Merges every running integral's segment totals in order into its out and
+// res, clears its flag, appends (I, var) to its iterations and decides
+// whether it stops (Weighted-Estimates, Check-Convergence, itmax).
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream);
 // Adjust-Bin-Bounds on the device for n_axes (integral, axis) pairs
 // (axis_item[2a], axis_item[2a+1]): reads the integral's histogram row from its

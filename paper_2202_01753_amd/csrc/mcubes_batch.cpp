@@ -19,8 +19,14 @@
 //      integral's segment totals, and the bin adjustment of the integrals
 //      still adjusting — on the device, so grids and histograms stay
 //      resident;
-//   4. reads back 4 doubles per integral and runs Weighted-Estimates and
-//      Check-Convergence on the host; finished integrals release their block.
+//   4. after the merge, Weighted-Estimates and Check-Convergence run on the
+//      device for every integral, which stops it there (its later segments
+//      do nothing) once it has converged or run out of iterations;
+//   5. reads back kResStride doubles per integral.
+// The steps are pipelined by one: a call launches the next step first and
+// only then waits for the previous one and retires the integrals it
+// stopped, so the device never waits for the host's bookkeeping, and the
+// upload, table staging and read-back buffers alternate between two copies.
 #include <cmath>
 #include <algorithm>
 #include <cstring>
@@ -32,6 +38,7 @@
 #include <unordered_map>
 
 #include "batch_plan.hpp"
+#include "estimate.hpp"
 #include "host.hpp"
 #include "internal.hpp"
 #include "mcubes.h"
@@ -84,8 +91,10 @@ struct Request {
     mc_status status = MC_OK;
     size_t block_off = 0, block_bytes = 0;
     size_t off_consts = 0, off_tables = 0, off_grid[2] = {0, 0}, off_out = 0;  // in the workspace
+    size_t off_iters = 0, off_state = 0;
     int cur = 0;     // current grid buffer
-    int it = 0;      // iterations done
+    int it = 0;      // iterations whose results the host has seen
+    int launched = 0;  // iterations launched (it, or one more while a step is in flight)
     std::vector<double> Is, Vs;
     double est[3] = {0.0, 0.0, NAN};
     int converged = 0;
@@ -113,7 +122,8 @@ double cube_cost(const mc_problem &pr, int64_t p) {
 
 // Bytes of an integral's persistent block and the offsets inside it.
 size_t block_layout(const Request &r, size_t *o_consts, size_t *o_tables, size_t *o_grid0,
-                    size_t *o_grid1, size_t *o_out) {
+                    size_t *o_grid1, size_t *o_out, size_t *o_iters = nullptr,
+                    size_t *o_state = nullptr) {
     const int d = r.prob.dim, nb = r.prob.nbins;
     const size_t real = fp32_of(r) ? sizeof(float) : sizeof(double);
     size_t off = 0;
@@ -127,6 +137,10 @@ size_t block_layout(const Request &r, size_t *o_consts, size_t *o_tables, size_t
     off = align_up(off + sizeof(double) * d * (nb + 1));
     *o_out = off;
     off = align_up(off + sizeof(double) * (4 + (size_t)d * nb));
+    if (o_iters) *o_iters = off;
+    off = align_up(off + sizeof(double) * 2 * (size_t)r.prob.itmax);
+    if (o_state) *o_state = off;
+    off = align_up(off + sizeof(uint32_t));
     return off;
 }
 
@@ -154,6 +168,10 @@ constexpr int kKernels = 4;
 int kernel_of(const Request &r) {
     return 2 * (fp32_of(r) ? 1 : 0) + (r.prob.integrand == MC_F_GAUSS_TABLES ? 1 : 0);
 }
+bool kernel_fp32(int kern) { return kern >= 2; }
+bool kernel_tables(int kern) { return kern % 2 == 1; }
+// Workgroups of kBatchBlock threads a CU can hold at the kernels' register use.
+constexpr int kMaxWgsPerCu = 4;
 // Launch groups per step: kernel x {integrals whose LDS footprint leaves the
 // kernel's register-limited occupancy, the rest}.
 constexpr int kGroups = 2 * kKernels;
@@ -212,7 +230,7 @@ StepLayout step_layout(const StepCounts &c) {
     off = align_up(off + sizeof(BatchSegment) * c.nseg);
     L.upload_end = off;
     L.res = off;
-    off = align_up(off + sizeof(double) * 4 * c.n);
+    off = align_up(off + sizeof(double) * kResStride * c.n);
     L.seg_tot = off;
     off = align_up(off + sizeof(double) * 4 * c.nseg);
     L.total = off;
@@ -253,24 +271,37 @@ struct mc_server {
     int64_t step_budget = 0;      // samples per step (0: every active request in every step)
     int32_t max_skip = 0;         // steps a request may be left out in a row under the budget
     StepNeed need;  // of the active set
-    Pinned staging;    // the step's upload
-    Pinned tab_stage;  // tables of the integrals admitted in this step
-    Pinned res_buf;  // the step's read-back: 4 doubles per integral
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    // Two of each, alternating between steps: the host fills one for the step
+    // it launches while the previous step may still read the other.
+    Pinned staging[2];    // the step's upload
+    Pinned tab_stage[2];  // tables of the integrals admitted in the step
+    Pinned res_buf[2];    // the step's read-back: kResStride doubles per integral
+    hipEvent_t ev[2][3] = {};  // per buffer: sampling start and end, step done
+    int buf = 0;               // the buffer of the next step launched
+    // The step launched and not yet read back: its buffer, the ids of the
+    // integrals it lists (in the order of its results) and its host time.
+    struct InFlight {
+        bool valid = false;
+        int buf = 0;
+        std::vector<int64_t> ids;
+        double host_ms = 0.0;
+    } inflight;
     mc_batch_stats stats{};
 
     ~mc_server() {
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto &b : ev)
+            for (auto &e : b)
+                if (e) (void)hipEventDestroy(e);
     }
 
     mc_status init() {
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        gcap = cus * 4;  // 256-thread workgroups: at most 4 per CU at the kernels' register use
-        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        gcap = cus * kMaxWgsPerCu;
+        for (auto &b : ev)
+            for (auto &e : b) HIP_TRY(hipEventCreate(&e));
         for (int k = 0; k < kKernels; ++k) {
-            HIP_TRY(allow_lds(batch_kernel(k >= 2, k % 2 == 1), kLdsDynamicLimit));
+            HIP_TRY(allow_lds(batch_kernel(kernel_fp32(k), kernel_tables(k)), kLdsDynamicLimit));
             mc_status st = occupancy(k, kBatchBlock, 0, &occ_full[k]);
             if (st != MC_OK) return st;
         }
@@ -297,7 +328,7 @@ struct mc_server {
         }
         int per_cu = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, batch_kernel(kern >= 2, kern % 2 == 1), threads, lds_q));
+            &per_cu, batch_kernel(kernel_fp32(kern), kernel_tables(kern)), threads, lds_q));
         per_cu = std::min(per_cu, gcap / cus);
         {
             std::lock_guard<std::mutex> lk(g_occ_mu);
@@ -361,14 +392,16 @@ struct mc_server {
             if (step_layout(worst_counts(grown, gcap)).total > step_cap) break;
             size_t off;
             if (!arena->alloc(r->block_bytes, &off)) break;
-            size_t oc, ot, og0, og1, oo;
-            block_layout(*r, &oc, &ot, &og0, &og1, &oo);
+            size_t oc, ot, og0, og1, oo, oi, os;
+            block_layout(*r, &oc, &ot, &og0, &og1, &oo, &oi, &os);
             r->block_off = off;
             r->off_consts = off + oc;
             r->off_tables = off + ot;
             r->off_grid[0] = off + og0;
             r->off_grid[1] = off + og1;
             r->off_out = off + oo;
+            r->off_iters = off + oi;
+            r->off_state = off + os;
             // constants and the starting grid travel with the step's upload
             // (admit_kernel); the tables are copied below
             const std::vector<double> c = axis_constants(&r->prob);
@@ -394,13 +427,15 @@ struct mc_server {
             if (!admitted[k]->tables.empty())
                 tab_bytes += align_up((fp32_of(*admitted[k]) ? sizeof(float) : sizeof(double)) * kTablesLen);
         if (tab_bytes) {
-            HIP_TRY(hipStreamSynchronize(stream));  // no copy from tab_stage is in flight
-            HIP_TRY(tab_stage.reserve(tab_bytes));
+            // this step's copy of the staging buffer: its last copies were two
+            // steps ago, which the previous call has waited for
+            Pinned &tab = tab_stage[buf];
+            HIP_TRY(tab.reserve(tab_bytes));
             size_t off = 0;
             for (size_t k = first_new; k < admitted.size(); ++k) {
                 const Request *r = admitted[k];
                 if (r->tables.empty()) continue;
-                char *dst = tab_stage.data() + off;
+                char *dst = tab.data() + off;
                 size_t bytes;
                 if (fp32_of(*r)) {
                     float *f = reinterpret_cast<float *>(dst);
@@ -449,24 +484,93 @@ struct mc_server {
         const auto t_start = std::chrono::steady_clock::now();
         mc_status st = admit();
         if (st != MC_OK) return st;
-        if (active.empty()) return MC_OK;
-        std::vector<Request *> idle;  // admitted, not run in this step
-        if (step_budget > 0) select_for_step(idle);
-        mc_status rs = run_step(n_finished, t_start);
+        InFlight next;
+        // integrals whose last iteration is in flight have certainly stopped:
+        // they wait for the read-back outside this step
+        std::vector<Request *> idle;  // not run in this step
+        {
+            std::vector<Request *> runnable;
+            for (Request *r : active) (r->launched < r->prob.itmax ? runnable : idle).push_back(r);
+            active.swap(runnable);
+        }
+        if (!active.empty()) {
+            if (step_budget > 0) select_for_step(idle);
+            st = launch_step(next);
+        }
         active.insert(active.end(), idle.begin(), idle.end());
+        if (st != MC_OK) return st;
+        const auto t_launched = std::chrono::steady_clock::now();
+        // the previous step's results, while the device runs this one
+        double collect_host_ms = 0.0;
+        if (inflight.valid) {
+            st = collect(inflight, n_finished, &collect_host_ms);
+            if (st != MC_OK) return st;
+        }
+        inflight = std::move(next);
+        if (inflight.valid) buf ^= 1;
         need = StepNeed{};
         for (Request *r : active) need.add(*r);
-        return rs;
+        const auto t_end = std::chrono::steady_clock::now();
+        stats.step_ms += std::chrono::duration<double, std::milli>(t_end - t_start).count();
+        stats.host_ms +=
+            std::chrono::duration<double, std::milli>(t_launched - t_start).count() + collect_host_ms;
+        return MC_OK;
     }
 
-    // One step over the requests in active; the finished ones leave it.
-    mc_status run_step(int32_t *n_finished, std::chrono::steady_clock::time_point t_start) {
+    // Waits for a launched step, then retires what it stopped: the
+    // integrals the device found converged, out of iterations or non-finite.
+    // (Integrals retired by an earlier step may be listed; they did nothing.)
+    mc_status collect(InFlight &f, int32_t *n_finished, double *host_ms) {
+        HIP_TRY(hipEventSynchronize(ev[f.buf][2]));
+        const auto t0 = std::chrono::steady_clock::now();
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[f.buf][0], ev[f.buf][1]));
+        const double *res = reinterpret_cast<const double *>(res_buf[f.buf].data());
+        bool worked = false;  // whether any integral listed still ran in this step
+        for (size_t k = 0; k < f.ids.size(); ++k) {
+            auto found = all.find(f.ids[k]);
+            if (found == all.end()) continue;  // released by the caller
+            Request *r = found->second.get();
+            if (r->state != MC_REQ_RUNNING) continue;
+            const double *q = res + (size_t)kResStride * k;
+            if (q[6] == kResSkipped) continue;
+            worked = true;
+            stats.calls += r->m * r->p;
+            r->it += 1;
+            r->Is.push_back(q[0]);
+            r->Vs.push_back(q[1]);
+            r->est[0] = q[3];
+            r->est[1] = q[4];
+            r->est[2] = q[5];
+            if (q[6] == (double)kItemFailed) {
+                finish(r, MC_REQ_FAILED, MC_ENONFINITE);
+                ++*n_finished;
+            } else if (q[6] == (double)kItemDone) {
+                r->converged = q[7] != 0.0 ? 1 : 0;
+                finish(r, MC_REQ_DONE, MC_OK);
+                ++*n_finished;
+            }
+        }
+        active.erase(std::remove_if(active.begin(), active.end(),
+                                    [](const Request *r) { return r->state != MC_REQ_RUNNING; }),
+                     active.end());
+        if (worked) stats.steps += 1;
+        stats.sample_ms += ms;
+        f.valid = false;
+        *host_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return MC_OK;
+    }
+
+    // Launches one step over the requests in active (nothing waits for it):
+    // the upload, admissions, sampling launches, merge and decision, bin
+    // adjustment and the read-back into this step's buffer; next describes it.
+    mc_status launch_step(InFlight &next) {
         mc_status st = MC_OK;
         // launch groups: the kernel, then whether the integral's LDS footprint
         // still allows the kernel's register-limited workgroups per CU
         for (Request *r : active) {
             const int kern = kernel_of(*r);
-            const size_t lds = lds_bytes_of(r->prob.dim, r->prob.nbins, r->it < r->prob.ita, kern >= 2);
+            const size_t lds = lds_bytes_of(r->prob.dim, r->prob.nbins, r->launched < r->prob.ita, kernel_fp32(kern));
             int o = 0;
             st = occupancy(kern, kBatchBlock, lds, &o);
             if (st != MC_OK) return st;
@@ -483,13 +587,13 @@ struct mc_server {
         int first[kGroups + 1] = {};
         for (int i = 0; i < n; ++i) {
             const Request *r = active[i];
-            const bool adjust = r->it < r->prob.ita;
+            const bool adjust = r->launched < r->prob.ita;
             if (adjust) {
                 n_axes += r->prob.one_d ? 1 : r->prob.dim;  // m-Cubes1D: axis 0, then copied
                 max_nb = std::max(max_nb, r->prob.nbins);
             }
             const int grp = r->group;
-            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, grp >= 4));
+            lds[grp] = std::max(lds[grp], lds_bytes_of(r->prob.dim, r->prob.nbins, adjust, kernel_fp32(grp / 2)));
             first[grp + 1] = i + 1;
         }
         for (int grp = 1; grp <= kGroups; ++grp) first[grp] = std::max(first[grp], first[grp - 1]);
@@ -537,8 +641,8 @@ struct mc_server {
         const StepLayout L = step_layout(counts);
         if (L.total > step_cap || (int64_t)segs.size() > worst_counts(need, gcap).nseg)
             return MC_EWORKSPACE;  // cannot happen: admission keeps the worst case within the area
-        HIP_TRY(staging.reserve(L.upload_end));
-        char *up = staging.data();
+        HIP_TRY(staging[buf].reserve(L.upload_end));
+        char *up = staging[buf].data();
         std::memset(up + L.flags, 0, L.axis_item - L.flags);  // flags and queue counters start at 0
         BatchItem *items = reinterpret_cast<BatchItem *>(up + L.items);
         int32_t *item_first_h = reinterpret_cast<int32_t *>(up + L.item_first);
@@ -547,15 +651,20 @@ struct mc_server {
         int ax = 0;
         for (int i = 0; i < n; ++i) {
             Request *r = active[i];
-            const bool adjust = r->it < r->prob.ita;
+            const bool adjust = r->launched < r->prob.ita;
             BatchItem &b = items[i];
             std::memset(&b, 0, sizeof(b));
             double *grid = reinterpret_cast<double *>(ws + r->off_grid[r->cur]);
-            sample_args(&r->prob, r->g, r->m, r->p, (uint32_t)r->it, adjust, ws + r->off_consts, grid,
-                        r->tables.empty() ? nullptr : ws + r->off_tables, &b.a);
+            sample_args(&r->prob, r->g, r->m, r->p, (uint32_t)r->launched, adjust, ws + r->off_consts,
+                        grid, r->tables.empty() ? nullptr : ws + r->off_tables, &b.a);
             b.grid = grid;
             b.out = reinterpret_cast<double *>(ws + r->off_out);
+            b.iters = reinterpret_cast<double *>(ws + r->off_iters);
+            b.state = reinterpret_cast<uint32_t *>(ws + r->off_state);
             b.alpha = r->prob.alpha;
+            b.tau_rel = r->prob.tau_rel;
+            b.chi2_max = r->prob.chi2_max;
+            b.itmax = r->prob.itmax;
             b.refine = adjust ? 1 : 0;
             next_grid[i] = reinterpret_cast<double *>(ws + r->off_grid[1 - r->cur]);
             if (adjust) {
@@ -584,6 +693,7 @@ struct mc_server {
             rec.consts = ws + r->off_consts;
             rec.grid = reinterpret_cast<double *>(ws + r->off_grid[0]);
             rec.out = reinterpret_cast<double *>(ws + r->off_out);
+            rec.state = reinterpret_cast<uint32_t *>(ws + r->off_state);
             rec.src = (int64_t)src;
             rec.const_words = (int32_t)(r->consts_img.size() / 4);
             rec.dim = r->prob.dim;
@@ -604,63 +714,36 @@ struct mc_server {
         A.flags = reinterpret_cast<uint32_t *>(step_base + L.flags);
         A.res = reinterpret_cast<double *>(step_base + L.res);
         A.n_items = n;
-        HIP_TRY(hipEventRecord(ev[0], stream));
+        HIP_TRY(hipEventRecord(ev[buf][0], stream));
         for (int grp = 0; grp < kGroups; ++grp) {
             if (!G[grp]) continue;
             A.queue = reinterpret_cast<uint32_t *>(step_base + L.queue) + grp;
             A.lo = seg_lo[grp];
             A.hi = seg_lo[grp + 1];
-            HIP_TRY(launch_batch(grp >= 4, grp / 2 % 2 == 1, G[grp], T[grp], lds[grp], stream, A));
+            HIP_TRY(launch_batch(kernel_fp32(grp / 2), kernel_tables(grp / 2), G[grp], T[grp], lds[grp], stream,
+                                 A));
         }
-        HIP_TRY(hipEventRecord(ev[1], stream));
+        HIP_TRY(hipEventRecord(ev[buf][1], stream));
         HIP_TRY(launch_batch_finalize(A, stream));
         HIP_TRY(allow_lds(batch_refine_symbol(), sizeof(double) * max_nb));
         HIP_TRY(launch_batch_refine(A.items, reinterpret_cast<const int32_t *>(step_base + L.axis_item),
                                     reinterpret_cast<double *const *>(step_base + L.next_grid), n_axes,
                                     max_nb, stream));
-        HIP_TRY(res_buf.reserve(sizeof(double) * 4 * (size_t)n));
-        const double *res = reinterpret_cast<const double *>(res_buf.data());
-        HIP_TRY(hipMemcpyAsync(res_buf.data(), A.res, sizeof(double) * 4 * n, hipMemcpyDeviceToHost,
-                               stream));
-        const auto t_launched = std::chrono::steady_clock::now();
-        HIP_TRY(hipStreamSynchronize(stream));
-        const auto t_synced = std::chrono::steady_clock::now();
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
-
-        // host steps of Alg. 2 per integral
-        std::vector<Request *> still;
-        still.reserve(n);
+        HIP_TRY(res_buf[buf].reserve(sizeof(double) * kResStride * (size_t)n));
+        HIP_TRY(hipMemcpyAsync(res_buf[buf].data(), A.res, sizeof(double) * kResStride * n,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipEventRecord(ev[buf][2], stream));
+        // the iterations launched, the grids the device adjusts into
+        next.valid = true;
+        next.buf = buf;
+        next.ids.resize(n);
         for (int i = 0; i < n; ++i) {
             Request *r = active[i];
-            const bool adjust = r->it < r->prob.ita;
-            stats.calls += r->m * r->p;
-            if (res[4 * i + 2] != 0.0) {
-                finish(r, MC_REQ_FAILED, MC_ENONFINITE);
-                ++*n_finished;
-                continue;
-            }
-            r->Is.push_back(res[4 * i]);
-            r->Vs.push_back(res[4 * i + 1]);
-            r->it += 1;
-            weighted(r->it, r->Is.data(), r->Vs.data(), r->est);
-            if (adjust) r->cur = 1 - r->cur;
-            const bool conv = check_convergence(&r->prob, r->it, r->est);
-            if (conv || r->it >= r->prob.itmax) {
-                r->converged = conv ? 1 : 0;
-                finish(r, MC_REQ_DONE, MC_OK);
-                ++*n_finished;
-            } else {
-                still.push_back(r);
-            }
+            next.ids[i] = r->id;
+            if (r->launched < r->prob.ita) r->cur = 1 - r->cur;
+            r->launched += 1;
         }
-        active.swap(still);
-        stats.steps += 1;
         stats.max_active = std::max<int32_t>(stats.max_active, n);
-        stats.sample_ms += ms;
-        const auto t_end = std::chrono::steady_clock::now();
-        stats.step_ms += std::chrono::duration<double, std::milli>(t_end - t_start).count();
-        stats.host_ms += std::chrono::duration<double, std::milli>((t_launched - t_start) + (t_end - t_synced)).count();
         return MC_OK;
     }
 };
@@ -767,7 +850,7 @@ mc_status mc_batch_workspace_bytes(const mc_problem *probs, int32_t n, size_t *b
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    *bytes = align_up(arena) + step_layout(worst_counts(need, cus * 4)).total;
+    *bytes = align_up(arena) + step_layout(worst_counts(need, cus * kMaxWgsPerCu)).total;
     return MC_OK;
 }
 
@@ -795,11 +878,12 @@ mc_status mc_batch_integrate(const mc_problem *probs, int32_t n, void *d_ws, siz
         st = srv->submit(&probs[i], &ids[i]);
         if (st != MC_OK) return st;
     }
-    while (!srv->active.empty() || !srv->queue.empty()) {
+    while (!srv->active.empty() || !srv->queue.empty() || srv->inflight.valid) {
         int32_t fin = 0;
         st = srv->step(&fin);
         if (st != MC_OK) return st;
-        if (srv->active.empty() && !srv->queue.empty()) return MC_EWORKSPACE;  // cannot admit
+        if (srv->active.empty() && !srv->queue.empty() && !srv->inflight.valid)
+            return MC_EWORKSPACE;  // cannot admit
     }
     for (int32_t i = 0; i < n; ++i) {
         const Request &r = *srv->all[ids[i]];

@@ -11,6 +11,7 @@
 // order (so the totals do not depend on which workgroup took which segment),
 // and a third adjusts the grids of the integrals still in their adjusting
 // iterations, on the device, so that grids and histograms never leave it.
+#include "estimate.hpp"
 #include "vsample.hpp"
 
 namespace mcubes {
@@ -74,7 +75,9 @@ __device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSeg
 // allocation, so the largest case sets it.  With the arguments read through
 // the constant address space every kernel fits 128 VGPRs (4 waves per SIMD);
 // the table integrand, the largest, still has a kernel of its own so that its
-// cases do not set the budget of the others.
+// cases do not set the budget of the others.  (Splitting the closed forms by
+// dimension, d <= 5 at 5 or 8 waves per SIMD, measured no faster: the extra
+// launch groups cost more per step than the occupancy gained.)
 template <bool F32, bool TABLES>
 __global__ void __launch_bounds__(kBatchMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 vsample_batch_kernel(const BatchArgs B) {
@@ -92,7 +95,12 @@ vsample_batch_kernel(const BatchArgs B) {
         const int si = ((Const<int32_t> *)B.order)[q];
         Const<BatchSegment> &sgc = ((Const<BatchSegment> *)B.segs)[si];
         const BatchSegment sg{sgc.item, 0, sgc.t0, sgc.t1};
-        Const<SampleArgs> &a = ((Const<BatchItem> *)B.items)[sg.item].a;
+        Const<BatchItem> &item = ((Const<BatchItem> *)B.items)[sg.item];
+        // an integral that stopped in an earlier step (the host had not yet
+        // seen it when it planned this one): nothing to do
+        const uint32_t state = *(const volatile uint32_t *)item.state;
+        if (__builtin_amdgcn_readfirstlane(state) != kItemRunning) continue;
+        Const<SampleArgs> &a = item.a;
         if constexpr (TABLES) {
             switch (a.kind) {
                 MC_CASE(3, 4) MC_CASE(3, 5) MC_CASE(3, 6) MC_CASE(3, 7) MC_CASE(3, 8) MC_CASE(3, 9)
@@ -113,28 +121,70 @@ vsample_batch_kernel(const BatchArgs B) {
 #undef MC_CASES_1_10
 #undef MC_CASE
 
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 64;  // one wavefront per integral
 
-// One thread per integral: its segment totals summed in segment order,
-// TwoSum-compensated.
+// One wavefront per integral: its segment totals merged with TwoSum, each
+// lane over a strided subset in segment order and then across the lanes in
+// a fixed butterfly (so the totals do not depend on which workgroup took
+// which segment; an integral of a served step can have thousands of
+// segments, too many for one lane); then the host steps of Alg. 2 that
+// decide whether it goes on (Weighted-Estimates over all its iterations,
+// Check-Convergence, the iteration cap), in the same code and roundings as
+// the host driver.
 __global__ void __launch_bounds__(kFinThreads) batch_finalize_kernel(const BatchArgs B) {
-    const int item = blockIdx.x * kFinThreads + threadIdx.x;
-    if (item >= B.n_items) return;
+    const int item = blockIdx.x, lane = threadIdx.x;
     const BatchItem &it = B.items[item];
+    double *r = B.res + (size_t)kResStride * item;
+    if (*it.state != kItemRunning) {  // stopped earlier; its segments did nothing
+        if (lane == 0) {
+            for (int i = 0; i < kResStride; ++i) r[i] = 0.0;
+            r[6] = kResSkipped;
+            B.flags[item] = 0u;
+        }
+        return;
+    }
     const int s0 = B.item_first[item], s1 = B.item_first[item + 1];
-    double *o = it.out;
     double sI = 0.0, cI = 0.0, sV = 0.0, cV = 0.0;
-    for (int s = s0; s < s1; ++s) {
+    for (int s = s0 + lane; s < s1; s += kFinThreads) {
         const double *q = B.seg_tot + 4 * (size_t)s;
         two_sum_merge(sI, cI, q[0], q[1]);
         two_sum_merge(sV, cV, q[2], q[3]);
     }
-    const double flag = B.flags[item] ? 1.0 : 0.0;
-    o[0] = B.res[4 * item] = sI + cI;
-    o[1] = B.res[4 * item + 1] = sV + cV;
-    o[2] = B.res[4 * item + 2] = flag;
-    o[3] = B.res[4 * item + 3] = 0.0;
+#pragma unroll
+    for (int off = kFinThreads / 2; off >= 1; off >>= 1) {
+        const double s2 = __shfl_xor(sI, off, 64), c2 = __shfl_xor(cI, off, 64);
+        const double v2 = __shfl_xor(sV, off, 64), e2 = __shfl_xor(cV, off, 64);
+        two_sum_merge(sI, cI, s2, c2);
+        two_sum_merge(sV, cV, v2, e2);
+    }
+    if (lane != 0) return;
+    double *o = it.out;
+    const double I = sI + cI, V = sV + cV;
+    const bool bad = B.flags[item] != 0u;
+    o[0] = r[0] = I;
+    o[1] = r[1] = V;
+    o[2] = r[2] = bad ? 1.0 : 0.0;
+    o[3] = 0.0;
     B.flags[item] = 0u;
+    double est[3] = {0.0, 0.0, NAN};
+    bool conv = false;
+    uint32_t state = kItemRunning;
+    if (bad) {
+        state = kItemFailed;
+    } else {
+        const int k = (int)it.a.iter + 1;  // iterations including this one
+        it.iters[k - 1] = I;
+        it.iters[it.itmax + k - 1] = V;
+        weighted_estimate(k, it.iters, it.iters + it.itmax, est);
+        conv = converged_after(k, est, it.tau_rel, it.chi2_max);
+        if (conv || k >= it.itmax) state = kItemDone;
+    }
+    if (state != kItemRunning) *it.state = state;
+    r[3] = est[0];
+    r[4] = est[1];
+    r[5] = est[2];
+    r[6] = (double)state;
+    r[7] = conv ? 1.0 : 0.0;
 }
 
 // Adjust-Bin-Bounds on the device, one block per (integral, axis): three-
@@ -152,6 +202,7 @@ batch_refine_kernel(const BatchItem *items, const int32_t *axis_item, double *co
     const int ax = blockIdx.x;
     const int item = axis_item[2 * ax], j = axis_item[2 * ax + 1];
     const BatchItem &it = items[item];
+    if (*it.state != kItemRunning) return;  // stopped: its grid is not used again
     const int nb = it.a.nb;
     double *C = it.out + 4 + (size_t)j * nb;
     const double *B = it.a.grid + (size_t)j * (nb + 1);
@@ -231,6 +282,7 @@ admit_kernel(const AdmitRecord *recs, const char *upload) {
     const double nbd = (double)r.nb;
     for (int i = threadIdx.x; i < r.dim * row; i += kAdmitThreads) r.grid[i] = (double)(i % row) / nbd;
     for (int i = threadIdx.x; i < 4 + r.dim * r.nb; i += kAdmitThreads) r.out[i] = 0.0;
+    if (threadIdx.x == 0) *r.state = kItemRunning;
 }
 
 }  // namespace
@@ -267,8 +319,7 @@ hipError_t launch_batch(bool fp32, bool tables, int blocks, int threads, size_t 
 }
 
 hipError_t launch_batch_finalize(const BatchArgs &args, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_finalize_kernel, dim3((args.n_items + kFinThreads - 1) / kFinThreads),
-                       dim3(kFinThreads), 0, stream, args);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(args.n_items), dim3(kFinThreads), 0, stream, args);
     return hipGetLastError();
 }
 
