@@ -1,4 +1,6 @@
-"""Builds libmcubes.so for gfx950 in-tree (hipcc, one object per source, in parallel).
+"""Builds libmcubes.so for gfx950 in-tree (hipcc, one object per source, in parallel),
+and the VALU issue-rate microbenchmark behind the benchmark's operation model
+(paper_2202_01753_amd/valu_rates).
 
     python -m paper_2202_01753_amd.build
 """
@@ -15,6 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIBRARY = os.path.join(PKG, "libmcubes.so")
+UBENCH_SRC = os.path.join(PKG, "ubench", "valu_rates.hip")
+UBENCH = os.path.join(PKG, "valu_rates")
 ARCH = "gfx950"
 
 # No implicit contraction of a*b+c: the sampling kernel and the host bin
@@ -49,12 +53,24 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+def build_ubench() -> str:
+    tmp = UBENCH + ".tmp"
+    cmd = [hipcc(), "-O3", "-std=c++17", *DEVICE, "-o", tmp, UBENCH_SRC]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, UBENCH)
+    return UBENCH
+
+
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    jobs = jobs or min(len(srcs) + 1, os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
+        ub = ex.submit(build_ubench)
         objs = list(ex.map(_compile, srcs))
+        ub.result()
     tmp = LIBRARY + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
