@@ -18,9 +18,11 @@ largest single-GPU configuration, in both precisions.
 
 The roofline entry is for the sampling kernel: its average launch duration
 comes from HIP events recorded by the library on the launch stream, and its
-algorithmic work is the per-sample VALU lane-operation count of the method's
-steps (one issue slot per full-rate instruction), times the samples per launch,
-against the chip's VALU issue rate.  Where the kernel's rocprofv3 summary was
+algorithmic work is the per-sample VALU work of the method's steps in issue
+slots (each instruction class at its measured cost: a full slot for the
+64-bit class, half for simple 32-bit operations, more for the exponential and
+the reciprocals), times the samples per launch, against the chip's issue rate
+of 64-bit-class instructions.  Where the kernel's rocprofv3 summary was
 taken from the same code, its measured VALU instructions per sample, issue
 ratio and HBM traffic are attached.  The CPU baseline times the FP64 oracle
 on this host, on one core and on one process per usable CPU (at most 16, one
@@ -43,59 +45,104 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes per clock at 2.4 GHz = VALU lane-op issue rate
-# (a wave64 full-rate VALU instruction occupies a SIMD for 4 clocks).
+# MI355X: 256 CUs x 4 SIMDs, each issuing one wave64 instruction of the
+# 64-bit class (FP64 add/mul/fma, 32x32->64 products) every 4 clocks, at
+# 2.4 GHz: 3.93e13 lane issue slots per second (the FP64 vector rate, 78.6
+# TFLOP/s counted as FMAs).
 CUS, LANES_PER_CU_CLK, CLOCK_HZ = 256, 64, 2.4e9
-VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 lane-ops/s
+VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 slots/s
+
+# Issue cost of each VALU instruction class in those slots, as measured on
+# gfx950 by paper_2202_01753_amd/ubench/valu_rates.hip (cycles per wave64
+# instruction per SIMD / 4): the 64-bit class, 32-bit products, funnel shifts,
+# shift-and-add and conversions take a full slot; simple 32-bit operations
+# (FP32 add, mul, min, floor and two-operand fmac; integer add; bitwise ops)
+# half of one; the three-operand v_fma_f32 3.5 cycles; v_exp_f32 about 10,
+# v_rcp_f32 8 and v_rcp_f64 16.  Compares and selects, not measured on their
+# own, count as simple 32-bit operations.
+SLOT_COST = {"full": 1.0, "half": 0.5, "fma32": 0.875, "exp32": 2.5, "rcp32": 2.0, "rcp64": 4.0}
 
 
-PHILOX_BLOCK_OPS = 17 + 18
+def _add(mix: dict, n: float = 1.0, **ops: float) -> None:
+    for k, v in ops.items():
+        mix[k] = mix.get(k, 0.0) + n * v
 
 
-def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float:
-    """Algorithmic VALU lane-operations per sample of the FP64 path (or of the
-    FP32-evaluation path with fp32 set).
+def op_mix(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> dict:
+    """Algorithmic VALU lane-operations per sample by issue class, for the
+    FP64 path (or the FP32-evaluation path with fp32 set): the method's steps
+    as gfx950 instructions, with work that is uniform across the wavefront or
+    invariant across a sub-cube's samples excluded.
 
-    Counted from the method's steps at one issue slot per full-rate VALU
-    instruction (measured on gfx950: 32x32->64 integer products, FP64 add/mul/
-    fma and conversions all issue at the full rate; v_rcp_f64, v_rcp_f32 count
-    4 and v_exp_f32 2; a three-input XOR is one v_bitop3_b32), with work that
-    is uniform across the wavefront or invariant across a sub-cube's samples
-    excluded:
                                 FP64 path                      FP32 evaluation
-      Philox4x32-10 block       17 products + 18 three-way XOR, ceil(d/2) blocks; ceil(d/4)
-      per axis                  20: uniform 5, coordinate 2,   15: uniform 3, coordinate 2,
-                                bin index and clamp 7, address bin index and clamp 5, address
-                                and width 2, point 2,          1, point 2, Jacobian 2
+      Philox4x32-10 block       17 products + 19 XOR (two-     the same, ceil(d/4) blocks
+                                and three-input), ceil(d/2)
+      per axis                  16: uniform 3 (two funnel      14: uniform 2, coordinate 2,
+                                shifts, subtract), coordinate  bin index and clamp 5,
+                                2, bin index and clamp 5,      address 1, point 2,
+                                address 1, width 1, point 2,   Jacobian 2
                                 Jacobian 2
       Gaussian product          3 per axis + exp 20            3 per axis + expf 10
-      corner peak               d fma + binary powering +      d fma + powering +
-                                division 13                    division 12
-      two bilinear tables       2 x 21 + 2 products (on top of the Gaussian), both paths
+      corner peak               d fma + binary powering +      the same in FP32 (division
+                                division 11 (one v_rcp_f64)    11, one v_rcp_f32)
+      two bilinear tables       2 x 20 + 2 products            2 x 18 + 2
       f J / (m p), finiteness   4                              6 (two widening conversions)
-      shifted sums              3 (p-1)/p
+      shifted sums              3 (p-1)/p (FP64 in both paths)
       bin contributions         1 + d addresses (adjusting iterations; 1 + 1 in m-Cubes1D)
-      per sub-cube, / p         variance 5, two compensated additions 14,
+      per sub-cube, / p         variance 5, two compensated additions 14 (FP64),
                                 digit odometer 4 d, digit conversion d
     """
     d = int(prob["dim"])
     _, _, p = g_m_p
     kind = prob["integrand"]
-    philox = math.ceil(d / (4 if fp32 else 2)) * PHILOX_BLOCK_OPS
-    per_axis = (15 if fp32 else 20) * d
-    expo, div = (10, 12) if fp32 else (20, 13)
-    if kind == "const":
-        f = 0
-    elif kind == "gauss_product":
-        f = 3 * d + expo
-    elif kind == "corner_peak":
-        e = d + 1
-        f = d + (e.bit_length() - 1) + (bin(e).count("1") - 1) + div
+    mix: dict = {}
+    _add(mix, math.ceil(d / (4 if fp32 else 2)), full=17, half=19)
+    if fp32:
+        _add(mix, d, full=3, half=10, fma32=1)
     else:
-        f = 3 * d + expo + 2 * 21 + 2
-    axes = 1 if prob.get("one_d") else d  # histogram rows (m-Cubes1D: the first axis only)
-    tail = (6 if fp32 else 4) + 3 * (p - 1) / p + ((1 + axes) if adjust else 0) + (19 + 5 * d) / p
-    return float(philox + per_axis + f + tail)
+        _add(mix, d, full=16)
+    if kind in ("gauss_product", "gauss_tables"):
+        if fp32:
+            _add(mix, d, half=3)
+            _add(mix, exp32=1, full=3, fma32=2, half=4)
+        else:
+            _add(mix, d, full=3)
+            _add(mix, full=18, half=2)
+    if kind == "corner_peak":
+        e = d + 1
+        powering = (e.bit_length() - 1) + (bin(e).count("1") - 1)
+        if fp32:
+            _add(mix, half=d + powering)
+            _add(mix, full=4, rcp32=1, fma32=3, half=3)
+        else:
+            _add(mix, full=d + powering + 10, rcp64=1)
+    if kind == "gauss_tables":
+        if fp32:
+            _add(mix, 2, full=6, half=9, fma32=3)
+            _add(mix, half=2)
+        else:
+            _add(mix, full=2 * 20 + 2)
+    if fp32:
+        _add(mix, full=5, half=1)
+    else:
+        _add(mix, full=3, half=1)
+    _add(mix, full=3 * (p - 1) / p)
+    if adjust:
+        axes = 1 if prob.get("one_d") else d  # histogram rows (m-Cubes1D: the first axis only)
+        _add(mix, full=1 + axes)
+    _add(mix, 1.0 / p, full=5 + 14 + d, half=4 * d)
+    return mix
+
+
+def ops_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float:
+    """VALU lane-operations per sample (all classes counted alike)."""
+    return float(sum(op_mix(prob, g_m_p, adjust, fp32).values()))
+
+
+def slots_per_sample(prob: dict, g_m_p, adjust: bool, fp32: bool = False) -> float:
+    """Issue slots per sample: op_mix weighted by SLOT_COST, the work the
+    roofline prices against VALU_PEAK_OPS."""
+    return float(sum(SLOT_COST[k] * v for k, v in op_mix(prob, g_m_p, adjust, fp32).items()))
 
 
 # The tables kernel's HBM traffic per launch comes from rocprofv3 FETCH_SIZE /
@@ -298,7 +345,7 @@ def bench_batch(args, M, W, torch):
     ops = 0.0
     for p in probs:
         gmp = M.shape(p["dim"], p["maxcalls"])
-        per = ops_per_sample(p, gmp, adjust=True, fp32=p["precision"] == "fp32")
+        per = slots_per_sample(p, gmp, adjust=True, fp32=p["precision"] == "fp32")
         ops += per * gmp[1] * gmp[2] * p["itmax"]
     ops *= args.steps
     line = _base_line(args, "batch_4096_mixed", calls / el, el / args.steps * 1e3,
@@ -427,22 +474,23 @@ def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profil
     avg_launch_s = sum(r.sample_ms for r in res) / launches / 1e3
     fp32 = precision == "fp32"
     ops = ops_per_sample(p, gmp, adjust=p["ita"] > 0, fp32=fp32)
-    achieved = ops * calls_per_iter / avg_launch_s
+    slots = slots_per_sample(p, gmp, adjust=p["ita"] > 0, fp32=fp32)
+    achieved = slots * calls_per_iter / avg_launch_s
     r0 = res[0]
     prof = (profiled(precision) if profiled_here else None) or {}
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": prof.get("traffic"),
             "kernel": "vsample_kernel" + (" (FP32-eval)" if fp32 else ""),
-            "avg_launch_ms": avg_launch_s * 1e3, "ops_per_sample": ops,
+            "avg_launch_ms": avg_launch_s * 1e3, "ops_per_sample": ops, "slots_per_sample": slots,
             "launch": {"blocks": r0.blocks, "threads": r0.threads, "lds_bytes": r0.lds_bytes}}
     if "valu_insts_per_sample" in prof:
-        # the compiled kernel's own count (rocprofv3 SQ_INSTS_VALU) at this launch time
+        # the compiled kernel's own instruction count (rocprofv3 SQ_INSTS_VALU)
+        # and its wave instructions x 4 cycles over the busy cycles (what the
+        # VALU would be occupied if every instruction took a full slot)
         roof["measured"] = {
             "valu_insts_per_sample": prof["valu_insts_per_sample"],
             "valu_issue_ratio": prof["valu_issue_ratio"],
-            "valu_lane_insts_per_s": prof["valu_insts_per_sample"] * calls_per_iter / avg_launch_s / 1e12,
-            "frac_of_issue_peak": prof["valu_insts_per_sample"] * calls_per_iter / avg_launch_s
-                                  / VALU_PEAK_OPS}
+            "valu_lane_insts_per_s": prof["valu_insts_per_sample"] * calls_per_iter / avg_launch_s / 1e12}
 
     # time to 1e-3 relative error, on a workspace of its own
     pt = dict(p, tau_rel=1e-3, seed=77)

@@ -292,11 +292,15 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
 // Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
 // independent evaluations interleave and hide each other's LDS and
 // transcendental latency, but both must fit in registers: in FP32 evaluation
-// they do (up to d = 11, d = 8 with tables) and the pair is 6% faster on the
-// table workload; in FP64 the pair spills to scratch memory (over 1 GB of
-// HBM writes per launch at d = 6), so FP64 keeps one sample at a time.
+// they do (up to d = 11, d = 8 with tables); in FP64 the pair spills to
+// scratch memory (over 1 GB of HBM writes per launch at d = 6), so FP64
+// keeps one sample at a time.  The FP32 table kernel at d = 6 also keeps one:
+// the pair needs 86 VGPRs, which allows one 1024-thread workgroup per CU (4
+// waves per SIMD), one sample at a time 69, which allows two 768-thread
+// workgroups (6 waves per SIMD, the LDS limit) and is 11% faster; the pair
+// had been 6% faster at the 4-wave shape.
 template <int F, int D, bool F32>
-constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 : D <= 11);
+constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 && D != 6 : D <= 11);
 
 // Whether the single-integral kernel keeps each axis's lower bound in vector
 // registers for the whole launch.  The point x = lo + span xu is one fma with

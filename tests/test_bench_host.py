@@ -17,13 +17,33 @@ _spec.loader.exec_module(B)
 
 def test_op_model_tables_workload():
     # d = 6 Gaussian x two tables, g = 19, p = 2: 3 Philox blocks (FP64) or 2
-    # (FP32-eval), 20 / 15 operations per axis, the integrand, and the tail
+    # (FP32-eval), 16 / 14 operations per axis, the integrand, and the tail
     prob = W.config_tables()
     shape = (19, 19 ** 6, 2)
-    assert B.ops_per_sample(prob, shape, adjust=True) == 344.0
-    assert B.ops_per_sample(prob, shape, adjust=True, fp32=True) == 271.0
+    assert B.op_mix(prob, shape, adjust=True) == {"full": 249.0, "half": 72.0}
+    assert B.ops_per_sample(prob, shape, adjust=True) == 321.0
+    assert B.slots_per_sample(prob, shape, adjust=True) == 249.0 + 72.0 / 2
+    mix32 = B.op_mix(prob, shape, adjust=True, fp32=True)
+    assert mix32 == {"full": 93.0, "half": 153.0, "fma32": 14.0, "exp32": 1.0}
+    assert B.slots_per_sample(prob, shape, adjust=True, fp32=True) == 93 + 153 / 2 + 14 * 0.875 + 2.5
     # No-Adjust drops the 1 + d histogram addresses
-    assert B.ops_per_sample(prob, shape, adjust=False) == 344.0 - 7
+    assert B.ops_per_sample(prob, shape, adjust=False) == 321.0 - 7
+
+
+def test_op_model_corner_peak_d8():
+    # 4 / 2 Philox blocks; d fma, x^9 by three squarings and one product, one
+    # correctly rounded division (one reciprocal in it)
+    prob = W.config_corner8()
+    shape = (12, 12 ** 8, 2)
+    mix = B.op_mix(prob, shape, adjust=True)
+    assert mix["rcp64"] == 1.0
+    assert B.ops_per_sample(prob, shape, adjust=True) == 339.0
+    mix32 = B.op_mix(prob, shape, adjust=True, fp32=True)
+    assert mix32["rcp32"] == 1.0 and "rcp64" not in mix32
+    # every slot cost is positive and at most a quarter-rate instruction's
+    assert all(0 < c <= 4 for c in B.SLOT_COST.values())
+    # the peak is the 64-bit-class issue rate of 256 CUs at 2.4 GHz
+    assert B.VALU_PEAK_OPS == 256 * 64 * 2.4e9
 
 
 def test_op_model_one_d_keeps_one_histogram_row():

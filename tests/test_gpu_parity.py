@@ -525,7 +525,10 @@ def _production_passes(prob, grids, noadjust=True):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_production_tables_d6(precision):
-    prob = W.config_tables(seed=4, maxcalls=10_000_000, itmax=3, precision=precision)
+    # FP32 evaluation runs 2048 x 768 lanes (two workgroups per CU): 16^6
+    # sub-cubes give each lane ten
+    maxcalls = 10_000_000 if precision == "fp64" else 2 * 16**6
+    prob = W.config_tables(seed=4, maxcalls=maxcalls, itmax=3, precision=precision)
     _production_passes(prob, [O.init_grid(6, 500), _random_grid(6, 500, 3)])
 
 
