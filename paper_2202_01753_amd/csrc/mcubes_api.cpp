@@ -47,13 +47,21 @@ mc_status blocks_for(const void *fn, int threads, size_t lds, int64_t m, int req
     HIP_TRY(allow_lds(fn, lds));
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
     if (per_cu < 1) return MC_EINVAL;
-    // Where several workgroups share a CU, launch four times as many as fit at
-    // once: the workgroups are smaller, and CUs that were handed fewer of them
-    // take more later, instead of idling for the rest of the launch (12% faster
-    // at d = 8 with two 768-thread workgroups per CU; one 1024-thread
-    // workgroup per CU gains nothing and keeps the resident count).
+    // Where several workgroups share a CU, launch more than fit at once: the
+    // workgroups are smaller, and CUs that were handed fewer of them take more
+    // later, instead of idling for the rest of the launch (four times as many:
+    // 12% faster at d = 8 with two 768-thread workgroups per CU; one 1024-thread
+    // workgroup per CU gains nothing and keeps the resident count).  Every
+    // workgroup also leaves a histogram partial for the finalize to read, so
+    // four times is taken only where each lane still has at least 100
+    // sub-cubes to do, twice otherwise (the FP32 d = 6 tables pass: 60 per
+    // lane at twice; at four times its merge took 31 us of a 0.66 ms pass).
     const int64_t resident = (int64_t)per_cu * cus;
-    int64_t want = requested > 0 ? requested : (per_cu > 1 ? 4 * resident : resident);
+    int64_t want = resident;
+    if (requested > 0)
+        want = requested;
+    else if (per_cu > 1)
+        want = m >= (int64_t)100 * 4 * resident * threads ? 4 * resident : 2 * resident;
     const int64_t useful = (m + threads - 1) / threads;
     if (requested <= 0) want = std::min(want, useful);
     *out = (int)std::max<int64_t>(1, std::min<int64_t>(want, 1 << 20));

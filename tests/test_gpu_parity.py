@@ -217,12 +217,22 @@ def test_default_launch_shape_follows_occupancy():
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     # d = 8, nb = 500: 64 KB of LDS per workgroup, so two fit per CU, and two of
     # 768 threads keep more waves resident than one of 1024; the launch takes
-    # four times the resident count (or fewer if the cubes run out first)
+    # four times the resident count where every lane still has 100 sub-cubes
+    # to do, twice otherwise (or fewer if the cubes run out first)
     c8 = W.corner_peak(8, 8, maxcalls=20_000_000, nbins=500, itmax=1)
     g, m, p = O.shape(8, 20_000_000)
+    assert m < 100 * 4 * (2 * cus) * 768
     r = M.integrate(c8, timing=True)
     assert (r.threads, r.lds_bytes) == (768, 64064)
-    assert r.blocks == min(4 * 2 * cus, -(-m // 768))
+    assert r.blocks == min(2 * 2 * cus, -(-m // 768))
+    big = W.corner_peak(8, 8, maxcalls=1_000_000_000, nbins=500, itmax=1)
+    g, m, p = O.shape(8, 1_000_000_000)
+    assert m >= 100 * 4 * (2 * cus) * 768
+    assert M.launch_shape(M.BoundProblem(big), adjust=True)[:2] == (4 * 2 * cus, 768)
+    # the FP32-eval d = 6 tables kernel: two 72 KB workgroups of 768 threads
+    # per CU, 13^6 sub-cubes at 1e7, launched twice over
+    t32 = W.config_tables(maxcalls=10_000_000, itmax=1, precision="fp32")
+    assert M.launch_shape(M.BoundProblem(t32), adjust=True)[:2] == (2 * 2 * cus, 768)
     # d = 6 tables: one 48 KB workgroup of 1024 threads per CU, launched once per CU
     t6 = W.config_tables(maxcalls=2_000_000, itmax=1)
     r6 = M.integrate(t6, timing=True)
@@ -525,8 +535,8 @@ def _production_passes(prob, grids, noadjust=True):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_production_tables_d6(precision):
-    # FP32 evaluation runs 2048 x 768 lanes (two workgroups per CU): 16^6
-    # sub-cubes give each lane ten
+    # FP32 evaluation runs 1024 x 768 lanes (two workgroups per CU, launched
+    # twice over): 16^6 sub-cubes give each lane twenty
     maxcalls = 10_000_000 if precision == "fp64" else 2 * 16**6
     prob = W.config_tables(seed=4, maxcalls=maxcalls, itmax=3, precision=precision)
     _production_passes(prob, [O.init_grid(6, 500), _random_grid(6, 500, 3)])
