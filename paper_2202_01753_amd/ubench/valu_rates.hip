@@ -85,6 +85,17 @@ struct Args {
         store(g.out, x);                                                          \
     }
 
+// y a + v with a per-lane y, so that the compiler can use the two-operand
+// form that accumulates into its destination
+#define ACC_KERNEL(NAME, T, EXPR)                                                 \
+    __global__ void NAME(Args g) {                                                \
+        T x[kChains];                                                             \
+        for (int i = 0; i < kChains; ++i) x[i] = (T)(threadIdx.x * 1e-3 + i);     \
+        const T a = (T)g.a, y = (T)(threadIdx.x * 1e-4 + 1.0);                    \
+        chains<false>(x, g.n, [=](T v) { return EXPR; }, g.clocks);               \
+        store(g.out, x);                                                          \
+    }
+
 #define UINT_KERNEL(NAME, T, EXPR)                                                \
     __global__ void NAME(Args g) {                                                \
         T x[kChains];                                                             \
@@ -108,6 +119,10 @@ UINT_KERNEL(lshl_add_u32, uint32_t, (v << 3) + p)
 UINT_KERNEL(bitop3_b32, uint32_t, __builtin_amdgcn_bitop3_b32(v, p, q, 0x96))
 UINT_KERNEL(mul_lo_u32, uint32_t, v * p)
 UINT_KERNEL(mul_hi_u32, uint32_t, __umulhi(v, p))
+UINT_KERNEL(alignbit_b32, uint32_t, __builtin_amdgcn_alignbit(v, p, 12))
+// accumulating forms (the chain runs through the addend)
+ACC_KERNEL(fmac_f32, float, __builtin_fmaf(y, a, v))
+ACC_KERNEL(fmac_f64, double, __builtin_fma(y, a, v))
 // steps of two
 UINT_KERNEL(cvt_f32_u32_pair, uint32_t, (uint32_t)(float)v)
 FLOAT_KERNEL(cvt_f64_i32_pair, true, double, threadIdx.x * 1e-3 + i, (double)(int)v)
@@ -116,7 +131,8 @@ FLOAT_KERNEL(floor_f64_add, false, double, threadIdx.x * 1e-3 + i, __builtin_flo
 FLOAT_KERNEL(min_f32_mul, false, float, threadIdx.x * 1e-3f + i, __builtin_fminf(v * a, b))
 FLOAT_KERNEL(min_f64_mul, false, double, threadIdx.x * 1e-3 + i, __builtin_fmin(v * a, b))
 FLOAT_KERNEL(exp_f32_mul, false, float, -1e-3f * i, __builtin_amdgcn_exp2f(v) * a)
-// reciprocal
+// reciprocals
+FLOAT_KERNEL(rcp_f32, false, float, 1.0f + 1e-3f * i, __builtin_amdgcn_rcpf(v))
 FLOAT_KERNEL(rcp_f64, false, double, 1.0 + 1e-3 * i, __builtin_amdgcn_rcp(v))
 
 using Kernel = void (*)(Args);
@@ -188,6 +204,9 @@ int main() {
         {"bitop3_b32", bitop3_b32, 12345.0, 777.0, "v_bitop3_b32"},
         {"mul_lo_u32", mul_lo_u32, 2654435769.0, 0.0, "v_mul_lo_u32"},
         {"mul_hi_u32", mul_hi_u32, 2654435769.0, 0.0, "v_mul_hi_u32"},
+        {"alignbit_b32", alignbit_b32, 12345.0, 0.0, "v_alignbit_b32"},
+        {"fmac_f32", fmac_f32, 1e-7, 0.0, "v_fmac_f32"},
+        {"fmac_f64", fmac_f64, 1e-7, 0.0, "v_fmac_f64"},
         {"cvt_f32_u32_pair", cvt_f32_u32_pair, 0.0, 0.0, "v_cvt_f32_u32 + v_cvt_u32_f32"},
         {"cvt_f64_i32_pair", cvt_f64_i32_pair, 0.0, 0.0, "v_cvt_i32_f64 + v_cvt_f64_i32"},
         {"floor_f32_add", floor_f32_add, 0.25, 0.0, "v_add_f32 + v_floor_f32"},
@@ -195,6 +214,7 @@ int main() {
         {"min_f32_mul", min_f32_mul, 1.0000001, 1e30, "v_mul_f32 + v_min_f32"},
         {"min_f64_mul", min_f64_mul, 1.0000001, 1e300, "v_mul_f64 + v_min_f64"},
         {"exp_f32_mul", exp_f32_mul, 0.5, 0.0, "v_exp_f32 + v_mul_f32"},
+        {"rcp_f32", rcp_f32, 0.0, 0.0, "v_rcp_f32"},
         {"rcp_f64", rcp_f64, 0.0, 0.0, "v_rcp_f64"},
     };
     int rc = 0;
