@@ -308,10 +308,10 @@ constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 && D != 6 : D <= 11);
 // instruction, so every sample moved lo into a vector register first (two
 // moves per axis in FP64, one in FP32).  Taken for the FP64 Gaussian and
 // table kernels of d = 6..8 (5% fewer VALU instructions at d = 6 and 8,
-// 1.5-1.7% faster) and the FP32 table kernel at d = 6 (2.4% fewer, 1.7%
-// faster), which keep their waves per SIMD; at lower d the extra registers
-// cost waves, at higher d they spill, and the d = 8 corner-peak and FP32
-// d = 8 kernels would lose the two workgroups per CU they run at.
+// 1.5-1.7% faster) and the FP32 table kernel at d = 6 (1.4% faster), which
+// keep their waves per SIMD; at lower d the extra registers cost waves, at
+// higher d they spill, and the d = 8 corner-peak and FP32 d = 8 kernels
+// would lose the two workgroups per CU they run at.
 template <int F, int D, bool F32>
 constexpr bool kLowInVgpr = F32 ? (F == 3 && D == 6) : ((F == 1 || F == 3) && D >= 6 && D <= 8);
 
