@@ -61,6 +61,8 @@ VALU_PEAK_OPS = CUS * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 slots/s
 # v_rcp_f32 8 and v_rcp_f64 16.  Compares and selects, not measured on their
 # own, count as simple 32-bit operations.
 SLOT_COST = {"full": 1.0, "half": 0.5, "fma32": 0.875, "exp32": 2.5, "rcp32": 2.0, "rcp64": 4.0}
+SLOT_OP = ("one lane's share of a 4-cycle VALU issue slot (64-bit class 1, simple 32-bit "
+           "instructions 1/2, v_fma_f32 0.875, v_exp_f32 2.5, v_rcp_f32 2, v_rcp_f64 4)")
 
 
 def _add(mix: dict, n: float = 1.0, **ops: float) -> None:
@@ -355,7 +357,7 @@ def bench_batch(args, M, W, torch):
                        "integrands": "Gaussian product / corner peak",
                        "step": "one whole batch to completion (mc_batch_integrate)"})
     line["roofline"] = {"bound": "alu", "achieved": ops / sample_s / 1e12,
-                        "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                        "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "op": SLOT_OP,
                         "frac": ops / sample_s / VALU_PEAK_OPS, "traffic": None,
                         "kernel": "vsample_batch_kernel",
                         "avg_launch_ms": sample_s / sum(s.steps for s in stats) * 1e3}
@@ -479,7 +481,7 @@ def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profil
     r0 = res[0]
     prof = (profiled(precision) if profiled_here else None) or {}
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": prof.get("traffic"),
+            "unit": "TOP/s", "op": SLOT_OP, "frac": achieved / VALU_PEAK_OPS, "traffic": prof.get("traffic"),
             "kernel": "vsample_kernel" + (" (FP32-eval)" if fp32 else ""),
             "avg_launch_ms": avg_launch_s * 1e3, "ops_per_sample": ops, "slots_per_sample": slots,
             "launch": {"blocks": r0.blocks, "threads": r0.threads, "lds_bytes": r0.lds_bytes}}
