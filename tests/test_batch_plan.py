@@ -19,8 +19,14 @@ def driver(tmp_path_factory):
     if cxx is None:
         pytest.skip("no host C++ compiler")
     exe = str(tmp_path_factory.mktemp("plan") / "batch_plan_check")
-    subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", "-I", os.path.join(ROOT, "paper_2202_01753_amd", "csrc"),
-                    os.path.join(HERE, "pins", "batch_plan_check.cpp"), "-o", exe], check=True)
+    # built with the address and undefined-behaviour sanitizers where the
+    # compiler has them, so that every check also runs the planning code
+    # under them (host code only)
+    src = os.path.join(HERE, "pins", "batch_plan_check.cpp")
+    inc = ["-I", os.path.join(ROOT, "paper_2202_01753_amd", "csrc")]
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+    if subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", *san, *inc, src, "-o", exe]).returncode != 0:
+        subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", *inc, src, "-o", exe], check=True)
     return exe
 
 
