@@ -160,3 +160,27 @@ def test_refine_1d_matches_oracle_bit_for_bit():
             grid = a
         rows = grid.reshape(d, nb + 1)
         assert all(np.array_equal(rows[0], rows[j]) for j in range(d))
+
+
+def test_header_is_plain_c_and_the_library_links_without_python(tmp_path):
+    """A C99 program (-pedantic -Werror) includes include/mcubes.h, names every
+    declared entry point, links straight against libmcubes.so and calls the
+    host-only ones."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = os.path.join(ROOT, "tests", "pins", "abi_from_c.c")
+    listed = set(re.findall(r"\(entry_fn\)(mc_\w+)", open(src).read()))
+    assert listed == set(_declared())
+    M.lib()  # built
+    libdir = os.path.dirname(M.LIBRARY)
+    exe = str(tmp_path / "abi_from_c")
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                    src, "-o", exe, f"-L{libdir}", "-l:libmcubes.so", f"-Wl,-rpath,{libdir}", "-lm"], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("ok")
+    assert "shape 19 47045881 2" in out.stdout
