@@ -46,7 +46,10 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
     c = (c + c2) + e;
 }
 
-constexpr int kFinBins = 32;                  // bins per histogram block
+// 16 bins per block and 16 groups of workgroup rows per bin: at d = 6,
+// nb = 500 that is 188 blocks, which spread the read of the partials over
+// most of the CUs (32 bins per block left 94 blocks and took 1.6x as long).
+constexpr int kFinBins = 16;                        // bins per histogram block
 constexpr int kFinGroups = kFinThreads / kFinBins;  // workgroup-row groups per bin
 
 // Blocks [0, nhb): kFinBins bins per block; for each bin, group q sums the
