@@ -557,6 +557,36 @@ def test_production_narrow_gaussian_d8(precision, g):
     _production_passes(prob, [O.init_grid(8, 500), _gauss_quantile_grid(prob)])
 
 
+# ---------------------------------------------------------------- whole passes at the benchmark sizes
+#
+# The production kernel at the benchmark's own size and launch shape (1e8
+# samples at d = 6 with the tables, 1e9 at d = 8 with the corner peak, both
+# precisions), one adjusting pass on a random grid, against the oracle's whole
+# pass over every sub-cube (spread over the host's CPUs): estimate, variance
+# and the full d x nb histogram, element by element.
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("config", ["tables_d6_1e8", "corner_peak_d8_1e9"])
+def test_whole_pass_at_benchmark_size(config, precision):
+    import oracle_pool as P
+
+    if config == "tables_d6_1e8":
+        prob = W.config_tables(seed=1, precision=precision)
+    else:
+        prob = W.config_corner8(seed=1, precision=precision)
+    d, nb = prob["dim"], prob["nbins"]
+    s = M.Sampler(prob)
+    bp = M.BoundProblem(prob)
+    assert M.launch_shape(s.bp, adjust=True) == M.launch_shape(bp, adjust=True)
+    grid = _random_grid(d, nb, 17)
+    label = f"{config} {precision}"
+    print(label, "shape", M.launch_shape(s.bp, adjust=True), "cubes", s.m, flush=True)
+    gpu = s.sample(1, grid, True)
+    gpu["nbins"] = nb
+    ref = P.vsample(prob, 1, grid, hist=True)
+    _compare_totals(gpu, ref, _positive_scale(ref), label, _tol(prob))
+
+
 def test_narrow_gaussian_d8_free_running_matches_oracle():
     """The whole run at 1e7 samples per iteration, five iterations: each
     iteration's estimate as the oracle's (which adapts the same way from the
