@@ -346,6 +346,67 @@ def test_refine_moves_bins_toward_large_contributions():
     assert np.sum(np.diff(out)) == pytest.approx(1.0, abs=nb * 2.0**-52)
 
 
+def test_refine_damping_exponent():
+    """Lepage's compression raises each bin's weight ratio to alpha: with alpha
+    near 0 every bin of a positive histogram weighs the same and the grid stays
+    where it is; a larger alpha sharpens the contrast, so more boundaries move
+    into the heavy region (a dropped or misplaced exponent fails one of these)."""
+    nb = 40
+    grid = O.init_grid(1, nb)
+    h = np.full(nb, 1e-3)
+    h[10:14] = 10.0
+    flat = O.refine(1, nb, 1e-12, h, grid)
+    assert np.allclose(flat, grid, rtol=0, atol=1e-9)
+    inside = [np.sum((O.refine(1, nb, a, h, grid) > 0.25) & (O.refine(1, nb, a, h, grid) < 0.35))
+              for a in (0.25, 0.75, 1.5, 3.0)]
+    assert inside == sorted(inside) and inside[-1] > inside[0]
+
+
+def test_refine_support_and_uniform_part():
+    """Contributions only in the first k bins: zero-weight bins get no
+    boundaries, so every new boundary (but the last, 1) lies within the
+    smoothed support [0, (k+1)/nb]; where the smoothed weight is flat the new
+    boundaries are equally spaced."""
+    nb, k = 50, 20
+    grid = O.init_grid(1, nb)
+    h = np.zeros(nb)
+    h[:k] = 1.0
+    out = O.refine(1, nb, 1.5, h, grid)
+    _grid_ok(out, nb)
+    assert np.all(out[:nb] <= (k + 1) / nb + 1e-15)
+    flat = out[(out > 1.0 / nb) & (out < (k - 2) / nb)]
+    assert len(flat) > 10
+    gaps = np.diff(flat)
+    assert np.allclose(gaps, gaps[0], rtol=1e-9)
+
+
+def test_refine_compression_is_the_logarithmic_mean():
+    """Lepage's compressed weight of a bin with share x = s_i/S is (1-x)/ln(1/x),
+    the logarithmic mean L(1, x), raised to alpha.  Pinned through an identity
+    rather than the formula: L(1, x) = integral over t in [0, 1] of x^t
+    (numerical quadrature here).  A histogram with two flat levels makes the
+    new boundaries equally spaced inside each level, with spacings inversely
+    proportional to the levels' weights, so the ratio of the spacings is
+    (L(1, x_b) / L(1, x_a))^alpha."""
+    from scipy.integrate import quad
+
+    nb, alpha = 60, 1.5
+    grid = O.init_grid(1, nb)
+    h = np.where(np.arange(nb) < 30, 4.0, 1.0)
+    out = O.refine(1, nb, alpha, h, grid)
+    _grid_ok(out, nb)
+    # smoothed: 4 in bins 0..28, 3 and 2 at the step, 1 in bins 31..59
+    S = 29 * 4.0 + 3.0 + 2.0 + 29 * 1.0
+    L = lambda x: quad(lambda t: x**t, 0.0, 1.0, epsabs=0, epsrel=1e-13)[0]
+    want = (L(1.0 / S) / L(4.0 / S)) ** alpha
+    a = out[(out > 1.0 / nb) & (out < 28.0 / nb)]
+    b = out[(out > 32.0 / nb) & (out < 59.0 / nb)]
+    assert len(a) > 10 and len(b) > 10
+    ga, gb = np.diff(a), np.diff(b)
+    assert np.allclose(ga, ga[0], rtol=1e-9) and np.allclose(gb, gb[0], rtol=1e-9)
+    assert ga[0] / gb[0] == pytest.approx(want, rel=1e-9)
+
+
 def test_refine_equal_shares():
     """New boundaries split the (piecewise uniform) compressed weight into equal shares."""
     rng = np.random.default_rng(12)
