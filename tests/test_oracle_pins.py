@@ -121,6 +121,26 @@ def test_map_uniform_dyadic_grid_is_identity():
         assert J == np.prod(hi - lo)
 
 
+def test_map_is_continuous_at_the_ends():
+    """The map is a piecewise-linear bijection of [0, 1] onto [lo, hi]: y = 0 goes
+    to lo and y = 1 (where the bin index would be nb) to hi, in the last bin with
+    that bin's Jacobian, and y just below 1 lands just below hi."""
+    rng = np.random.default_rng(21)
+    nb = 37
+    grid = np.concatenate([_random_grid(rng, nb), _random_grid(rng, nb)])
+    lo, hi = np.array([-2.0, 0.5]), np.array([3.0, 4.0])
+    x, bins, J = O.map_point(nb, grid, lo, hi, [1.0, 1.0])
+    assert np.array_equal(bins, [nb - 1, nb - 1])
+    assert np.allclose(x, hi, rtol=0, atol=1e-15)
+    want_J = np.prod([(1.0 - grid[j * (nb + 1) + nb - 1]) * nb * (hi[j] - lo[j]) for j in range(2)])
+    assert J == pytest.approx(want_J, rel=1e-14)
+    x0, bins0, _ = O.map_point(nb, grid, lo, hi, [0.0, 0.0])
+    assert np.array_equal(bins0, [0, 0]) and np.array_equal(x0, lo)
+    y = 1.0 - 2.0**-40
+    xb, _, _ = O.map_point(nb, grid, lo, hi, [y, y])
+    assert np.all(xb < hi) and np.all(hi - xb < 1e-9)
+
+
 def _random_grid(rng, nb):
     w = rng.gamma(0.7, size=nb)
     b = np.concatenate([[0.0], np.cumsum(w) / w.sum()])
