@@ -31,6 +31,10 @@ MUTANTS = [
      "    double along0 = lerp(t00, t01, tx);\n    double along1 = lerp(t10, t11, tx);", "table_integrand_nodes"),
     ("uniform X 2^-52", "    uint64_t odd = 2u * X + 1u;            /* < 2^53: exact in a double */\n"
      "    return (double)odd * 0x1p-53;", "    return (double)X * 0x1p-52;", "uniform_endpoints"),
+    ("uniform from a mis-shifted low word", "uint64_t X = ((uint64_t)whi << 20) | (uint64_t)(wlo >> 12);",
+     "uint64_t X = ((uint64_t)whi << 20) | (uint64_t)(wlo >> 11);", "uniform_endpoints"),
+    ("no refinement", "        orc_weighted(k, Is, Vs, &Ibar, &sigma, &chi2);\n        if (adjust) {",
+     "        orc_weighted(k, Is, Vs, &Ibar, &sigma, &chi2);\n        if (0) {", "integrate_closed_forms"),
     ("weights 1/sigma", "        double w = 1.0 / var[i];\n        W = W + w;",
      "        double w = 1.0 / sqrt(var[i]);\n        W = W + w;", "weighted_hand_cases"),
     ("chi2 over n", "chi / (double)(n - 1)", "chi / (double)(n)", "weighted_hand_cases"),
