@@ -50,6 +50,13 @@ MUTANTS = [
     ("edge bin not smoothed", "sm[0] = (C[0] + C[1]) / 2.0;", "sm[0] = C[0];", "uniform_and_degenerate"),
     ("smoothing over 2", "sm[i] = ((C[i - 1] + C[i]) + C[i + 1]) / 3.0;", "sm[i] = ((C[i - 1] + C[i]) + C[i + 1]) / 2.0;",
      "uniform_and_degenerate or logarithmic_mean"),
+    ("float uniform from 24 bits", "    uint32_t odd = 2u * (w >> 9) + 1u;", "    uint32_t odd = 2u * (w >> 8) + 1u;",
+     "fp32 or uniform"),
+    ("float table axes swapped", "return lerpf_(lerpf_(t00, t10, tx), lerpf_(t01, t11, tx), ty);",
+     "return lerpf_(lerpf_(t00, t01, tx), lerpf_(t10, t11, tx), ty);", "fp32_eval_tracks"),
+    ("float Gaussian exp(-acc/2)", "    float G = expf(-acc);", "    float G = expf(-0.5f * acc);", "fp32_eval_tracks"),
+    ("float corner-peak power d", "S = fmaf(K->pa[j], x[j], S);\n        unsigned e = (unsigned)(d + 1);",
+     "S = fmaf(K->pa[j], x[j], S);\n        unsigned e = (unsigned)(d);", "fp32_eval_tracks"),
     ("one adjusting iteration too many", "        int adjust = it < P->ita;\n        rc = orc_vsample",
      "        int adjust = it <= P->ita;\n        rc = orc_vsample", "resume_reproduces"),
 ]
