@@ -315,6 +315,18 @@ constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 && D != 6 : D <= 11);
 template <int F, int D, bool F32>
 constexpr bool kLowInVgpr = F32 ? (F == 3 && D == 6) : ((F == 1 || F == 3) && D >= 6 && D <= 8);
 
+// Whether the compiler is told that the kernel runs at exactly 4 waves per
+// SIMD (amdgpu_waves_per_eu(4, 4)), so that it schedules for that occupancy
+// rather than for a higher one the kernel cannot reach: the FP64 Gaussian
+// kernels of d = 6..8 and table kernels of d = 6, 7 (108-128 VGPRs, one
+// 1024-thread workgroup per CU either way); 0.6% faster at d = 6 with the
+// tables and 0.8% at d = 8 with the Gaussian.  (At d = 8 with the tables it
+// would spill 12 bytes.)  The others keep the compiler's own range (1 to 8
+// waves, which compiles to the same code as no attribute).
+template <int F, int D, bool TRACE, bool F32>
+constexpr bool kFourWaves =
+    !F32 && !TRACE && ((F == 1 && D >= 6 && D <= 8) || (F == 3 && (D == 6 || D == 7)));
+
 // All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
 // contributions to the LDS histogram when collecting them, and records the
 // cube in the trace when tracing.  PAIR: evaluate the samples two at a time
@@ -614,7 +626,9 @@ __device__ __forceinline__ void block_totals(double sI, double cI, double sV, do
 // the sub-cubes [t0, t1); F32 instantiations evaluate the map and the
 // integrand in single precision.  Everything from I_k on is FP64 in both.
 template <int F, int D, bool TRACE, bool F32>
-__global__ void __launch_bounds__(kMaxBlock) vsample_kernel(const SampleArgs a) {
+__global__ void __launch_bounds__(kMaxBlock)
+    __attribute__((amdgpu_waves_per_eu(kFourWaves<F, D, TRACE, F32> ? 4 : 1, kFourWaves<F, D, TRACE, F32> ? 4 : 8)))
+    vsample_kernel(const SampleArgs a) {
     extern __shared__ double lds[];
     const LdsView<F32> v(lds, D, a.nb);
     load_lds<D, F32>(a, v);
