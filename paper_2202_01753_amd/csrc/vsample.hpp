@@ -315,17 +315,23 @@ constexpr bool kPairSamples = F32 && (F == 3 ? D <= 8 && D != 6 : D <= 11);
 template <int F, int D, bool F32>
 constexpr bool kLowInVgpr = F32 ? (F == 3 && D == 6) : ((F == 1 || F == 3) && D >= 6 && D <= 8);
 
-// Whether the compiler is told that the kernel runs at exactly 4 waves per
-// SIMD (amdgpu_waves_per_eu(4, 4)), so that it schedules for that occupancy
-// rather than for a higher one the kernel cannot reach: the FP64 Gaussian
-// kernels of d = 6..8 and table kernels of d = 6, 7 (108-128 VGPRs, one
-// 1024-thread workgroup per CU either way); 0.6% faster at d = 6 with the
-// tables and 0.8% at d = 8 with the Gaussian.  (At d = 8 with the tables it
-// would spill 12 bytes.)  The others keep the compiler's own range (1 to 8
-// waves, which compiles to the same code as no attribute).
+// The waves per SIMD the compiler is told a kernel runs at, where that is
+// fixed by its launch (amdgpu_waves_per_eu(w, w)), so that it schedules for
+// that occupancy rather than for a higher one the kernel cannot reach; 0: the
+// compiler's own range (1 to 8 waves, which compiles to the same code as no
+// attribute).  4 for the FP64 Gaussian kernels of d = 6..8 and table kernels
+// of d = 6, 7 (108-128 VGPRs, one 1024-thread workgroup per CU either way):
+// 0.6% faster at d = 6 with the tables, 0.8% at d = 8 with the Gaussian (at
+// d = 8 with the tables it would spill 12 bytes).  6 for the FP32 table
+// kernel at d = 6 (two 72 KB workgroups of 768 threads per CU): 0.6% faster;
+// the d = 8 corner-peak kernels, also at 6 by their LDS, measured 0.5-1.5%
+// slower with it.
 template <int F, int D, bool TRACE, bool F32>
-constexpr bool kFourWaves =
-    !F32 && !TRACE && ((F == 1 && D >= 6 && D <= 8) || (F == 3 && (D == 6 || D == 7)));
+constexpr int kFixedWaves =
+    TRACE ? 0
+          : (!F32 && ((F == 1 && D >= 6 && D <= 8) || (F == 3 && (D == 6 || D == 7)))) ? 4
+          : (F32 && F == 3 && D == 6) ? 6
+                                      : 0;
 
 // All p samples of sub-cube t (digits dig): returns I_t and var_t, adds the bin
 // contributions to the LDS histogram when collecting them, and records the
@@ -627,7 +633,8 @@ __device__ __forceinline__ void block_totals(double sI, double cI, double sV, do
 // integrand in single precision.  Everything from I_k on is FP64 in both.
 template <int F, int D, bool TRACE, bool F32>
 __global__ void __launch_bounds__(kMaxBlock)
-    __attribute__((amdgpu_waves_per_eu(kFourWaves<F, D, TRACE, F32> ? 4 : 1, kFourWaves<F, D, TRACE, F32> ? 4 : 8)))
+    __attribute__((amdgpu_waves_per_eu(kFixedWaves<F, D, TRACE, F32> ? kFixedWaves<F, D, TRACE, F32> : 1,
+                                       kFixedWaves<F, D, TRACE, F32> ? kFixedWaves<F, D, TRACE, F32> : 8)))
     vsample_kernel(const SampleArgs a) {
     extern __shared__ double lds[];
     const LdsView<F32> v(lds, D, a.nb);
