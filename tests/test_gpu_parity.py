@@ -566,19 +566,31 @@ def test_production_narrow_gaussian_d8(precision, g):
 # and the full d x nb histogram, element by element.
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("config", ["tables_d6_1e8", "corner_peak_d8_1e9"])
+@pytest.mark.parametrize("config", ["tables_d6_1e8", "corner_peak_d8_1e9", "narrow_gaussian_d8_1e9",
+                                    "symmetric_corner_d8_1e9_one_d"])
 def test_whole_pass_at_benchmark_size(config, precision):
     import oracle_pool as P
 
     if config == "tables_d6_1e8":
         prob = W.config_tables(seed=1, precision=precision)
-    else:
+    elif config == "corner_peak_d8_1e9":
         prob = W.config_corner8(seed=1, precision=precision)
+    elif config == "narrow_gaussian_d8_1e9":
+        prob = W.config_gauss8(seed=1, precision=precision)
+    else:
+        prob = W.config_symmetric8(seed=1, precision=precision, one_d=1)
     d, nb = prob["dim"], prob["nbins"]
     s = M.Sampler(prob)
     bp = M.BoundProblem(prob)
     assert M.launch_shape(s.bp, adjust=True) == M.launch_shape(bp, adjust=True)
-    grid = _random_grid(d, nb, 17)
+    # the w = 0.01 Gaussian on a grid of equal Gaussian mass, where its samples
+    # are not almost all zero; the m-Cubes1D pass on one shared random grid
+    if config == "narrow_gaussian_d8_1e9":
+        grid = _gauss_quantile_grid(prob)
+    elif prob.get("one_d"):
+        grid = np.tile(_random_grid(1, nb, 17), d)
+    else:
+        grid = _random_grid(d, nb, 17)
     label = f"{config} {precision}"
     print(label, "shape", M.launch_shape(s.bp, adjust=True), "cubes", s.m, flush=True)
     gpu = s.sample(1, grid, True)
