@@ -5,9 +5,10 @@
                     [--precision fp64|fp32] [--no-cpu-baseline] [--no-corner8]
 
 One step is one complete m-Cubes run (mc_integrate_prepared: every
-iteration of sampling kernel + fixed-order reduction + read-back + host
-weighting, bin adjustment and convergence check) on the workload's synthetic
-inputs; the workspace is allocated and the integrand's constants and tables
+iteration of sampling kernel, fixed-order reduction, weighting, convergence
+check and bin adjustment) on the workload's synthetic inputs, with the steps
+between passes on the device (device_steps; --host-steps runs them on the
+host, and the default run reports that figure beside the headline one); the workspace is allocated and the integrand's constants and tables
 are uploaded (mc_prepare) before the timed region, so the inputs are resident
 in device memory when it starts.  `value` is integrand samples per second
 over the K timed steps (iterations * m * p per step) of the FP64 path; the
@@ -448,11 +449,14 @@ def bench_serve(args, M, W, torch):
     print(json.dumps(line))
 
 
-def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profiled_here):
+def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profiled_here,
+                   device_steps=True):
     """K full runs of one problem in one precision on a prepared workspace
-    (inputs resident), the sampling kernel's HIP-event time and roofline, and
-    the wall time of one run to a 1e-3 relative error (after one untimed run)."""
-    p = dict(prob, precision=precision)
+    (inputs resident, no per-kernel timing: the throughput), then K more with
+    the library's HIP-event timing (the sampling kernel's launch time and
+    roofline), and the wall time of one run to a 1e-3 relative error (the
+    median of five, after one untimed run)."""
+    p = dict(prob, precision=precision, device_steps=device_steps)
     bp = M.BoundProblem(p, args.blocks, args.threads)
     ws = M.Workspace(bp)
     M.prepare(p, ws, bp=bp)
@@ -467,18 +471,19 @@ def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profil
     res = []
     t0 = time.perf_counter()
     for k in range(steps):
-        res.append(run(1 + k, timing=True))
+        res.append(run(1 + k))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    timed = [run(1 + k, timing=True) for k in range(steps)]
     gmp = M.shape(p["dim"], p["maxcalls"])
     calls_per_iter = gmp[1] * gmp[2]
-    launches = sum(r.iterations for r in res)
-    avg_launch_s = sum(r.sample_ms for r in res) / launches / 1e3
+    launches = sum(r.iterations for r in timed)
+    avg_launch_s = sum(r.sample_ms for r in timed) / launches / 1e3
     fp32 = precision == "fp32"
     ops = ops_per_sample(p, gmp, adjust=p["ita"] > 0, fp32=fp32)
     slots = slots_per_sample(p, gmp, adjust=p["ita"] > 0, fp32=fp32)
     achieved = slots * calls_per_iter / avg_launch_s
-    r0 = res[0]
+    r0 = timed[0]
     prof = (profiled(precision) if profiled_here else None) or {}
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s", "op": SLOT_OP, "frac": achieved / VALU_PEAK_OPS, "traffic": prof.get("traffic"),
@@ -501,16 +506,20 @@ def measure_single(args, M, torch, prob, precision, steps, warmup, exact, profil
     M.prepare(pt, wst, bp=bpt)
     M.integrate(pt, ws=wst, bp=bpt, prepared=True)
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    rt = M.integrate(pt, ws=wst, bp=bpt, prepared=True)
-    torch.cuda.synchronize()
-    tt = time.perf_counter() - t
+    walls = []
+    for _ in range(5):
+        t = time.perf_counter()
+        rt = M.integrate(pt, ws=wst, bp=bpt, prepared=True)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+    tt = sorted(walls)[len(walls) // 2]
     return {"value": sum(r.calls for r in res) / elapsed, "unit": "samples/s",
             "ms_per_step": elapsed / steps * 1e3, "calls_per_iter": calls_per_iter,
             "kernel_samples_per_s": calls_per_iter / avg_launch_s,
-            "finalize_ms_per_iter": sum(r.finalize_ms for r in res) / launches,
+            "finalize_ms_per_iter": sum(r.finalize_ms for r in timed) / launches,
             "roofline": roof,
-            "time_to_1e-3": {"ms": tt * 1e3, "iterations": rt.iterations, "converged": rt.converged,
+            "time_to_1e-3": {"ms": tt * 1e3, "min_ms": min(walls) * 1e3, "runs": len(walls),
+                             "iterations": rt.iterations, "converged": rt.converged,
                              "estimate": rt.estimate,
                              "rel_error": rt.error / abs(rt.estimate) if rt.estimate else None,
                              "chi2_dof": rt.chi2_dof,
@@ -539,6 +548,8 @@ def main():
                     help="serve: samples per server step, least remaining work first (0: no budget)")
     ap.add_argument("--max-skip", type=int, default=8,
                     help="serve: steps a request may be left out in a row under the budget")
+    ap.add_argument("--host-steps", action="store_true",
+                    help="run the steps between sampling passes on the host for every figure")
     ap.add_argument("--one-d", action="store_true",
                     help="the m-Cubes1D variant (one shared grid; for symmetric integrands)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -584,10 +595,19 @@ def main():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import closed_forms as CF
 
+    dev = not args.host_steps
     m64 = measure_single(args, M, torch, prob, "fp64", args.steps, args.warmup, CF.exact(prob),
-                         on_tables)
+                         on_tables, dev)
     m32 = measure_single(args, M, torch, prob, "fp32", args.steps, args.warmup, CF.exact(prob),
-                         on_tables)
+                         on_tables, dev)
+    host_steps = {}
+    if dev:
+        # the same runs with the steps between passes on the host
+        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_eval")):
+            h = measure_single(args, M, torch, prob, prec, args.steps, args.warmup, CF.exact(prob),
+                               False, False)
+            host_steps[key] = {"value": h["value"], "ms_per_step": h["ms_per_step"],
+                               "time_to_1e-3_ms": h["time_to_1e-3"]["ms"]}
     r0 = m64.pop("first")
     m32.pop("first")
     first32 = m32.pop("first_estimate")
@@ -611,12 +631,15 @@ def main():
         "config": {"workload": name, "dim": prob["dim"], "maxcalls": prob["maxcalls"],
                    "calls_per_iter": m64["calls_per_iter"], "nbins": prob["nbins"],
                    "itmax": prob["itmax"], "alpha": prob["alpha"],
-                   "step": "one full m-Cubes run (mc_integrate_prepared, inputs resident)"},
+                   "step": "one full m-Cubes run (mc_integrate_prepared, inputs resident)",
+                   "steps_between_passes": "device" if dev else "host"},
     }
     line.update(m64)
     line["estimate"] = {"value": r0.estimate, "error": r0.error, "chi2_dof": r0.chi2_dof,
                         "exact": CF.exact(prob)}
     line["fp32_eval"] = m32
+    if host_steps:
+        line["host_steps"] = host_steps
     if args.workload == "tables" and not args.no_corner8:
         # the largest single-GPU configuration beside it: d = 8 corner peak at
         # 1e9 samples per iteration, 20 iterations, in both precisions
@@ -624,7 +647,7 @@ def main():
         k = max(1, min(args.steps, 3))
         sub = {}
         for prec in ("fp64", "fp32"):
-            r = measure_single(args, M, torch, c8, prec, k, 1, CF.exact(c8), False)
+            r = measure_single(args, M, torch, c8, prec, k, 1, CF.exact(c8), False, dev)
             r.pop("first")
             r.pop("first_estimate")
             sub["fp64" if prec == "fp64" else "fp32_eval"] = r

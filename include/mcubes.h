@@ -94,7 +94,19 @@ typedef struct mc_problem {
                                 counts a run as converged only with a small chi^2); 0 selects
                                 MC_CHI2_DOF_DEFAULT, a negative value leaves chi^2 unchecked;
                                 not NaN */
+    int32_t device_steps;    /* 1: mc_integrate and mc_integrate_prepared run the steps of Alg. 2
+                                between sampling passes (Weighted-Estimates, Check-Convergence,
+                                Adjust-Bin-Bounds) on the device, so the passes of a run follow
+                                each other with no host round trip.  The bin adjustment takes the
+                                host's steps with its sums in a fixed order of its own and the
+                                device library's pow and log, so its boundaries agree with
+                                mc_refine_grid's to rounding, not bit for bit.  Taken for
+                                nbins <= MC_DEVICE_STEPS_MAX_BINS; above that, and in
+                                mc_integrate_noalloc, the host runs the steps.  0: the host runs
+                                them (the grid is then exactly mc_refine_grid's). */
 } mc_problem;
+
+#define MC_DEVICE_STEPS_MAX_BINS 4000
 
 #define MC_CHI2_DOF_DEFAULT 5.0
 
@@ -113,7 +125,9 @@ typedef struct mc_result {
  * stream around each kernel launch. */
 typedef struct mc_timing {
     double sample_ms;    /* sum over iterations of the sampling kernel */
-    double finalize_ms;  /* sum over iterations of the reduction kernel */
+    double finalize_ms;  /* sum over iterations of the reduction kernel (with device_steps:
+                            of everything after the sampling kernel, the decision and the
+                            bin adjustment included) */
     int32_t launches;    /* sampling-kernel launches */
     int32_t blocks;      /* workgroups per sampling launch */
     int32_t threads;     /* threads per workgroup */
@@ -178,6 +192,20 @@ mc_status mc_refine_grid(int32_t dim, int32_t nbins, double alpha, const double 
  * axis.  Host only; h_grid is updated in place. */
 mc_status mc_refine_grid_1d(int32_t dim, int32_t nbins, double alpha, const double *h_hist,
                             double *h_grid);
+
+/* mc_refine_grid (one_d == 0) or mc_refine_grid_1d (one_d == 1) on the
+ * device, as runs with device_steps take it: the same steps, one workgroup
+ * per axis, with the sums formed in a fixed order of its own and the device
+ * library's pow and log, so the boundaries agree with the host call's to
+ * rounding (deterministic: the same input gives the same output).
+ *   d_hist   device, dim*nbins contributions (row 0 only when one_d)
+ *   d_grid   device, dim*(nbins+1) boundaries, updated in place
+ * Queued on the stream; returns without waiting.  MC_EINVAL for dim outside
+ * 1..MC_MAX_DIM, nbins outside 2..MC_DEVICE_STEPS_MAX_BINS, alpha not
+ * positive and finite, one_d not 0 or 1, or a NULL pointer; MC_EDEVICE if the
+ * launch fails. */
+mc_status mc_refine_grid_device(int32_t dim, int32_t nbins, double alpha, int32_t one_d,
+                                const double *d_hist, double *d_grid, void *stream);
 
 /* Init-Bins (Alg. 2): nbins equal bins per axis.  Host only. */
 mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid);

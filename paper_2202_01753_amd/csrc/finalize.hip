@@ -1,5 +1,10 @@
-// Fixed-order reduction of the per-workgroup partials of one sampling pass,
-// and the dispatch of the sampling kernels by (integrand, dimension).
+// Fixed-order reduction of the per-workgroup totals and the histogram
+// accumulators of one sampling pass (with the decision that follows it when
+// the steps of Alg. 2 run on the device), and the dispatch of the sampling
+// kernels by (integrand, dimension).
+#include <algorithm>
+
+#include "estimate.hpp"
 #include "internal.hpp"
 
 namespace mcubes {
@@ -46,37 +51,63 @@ __device__ __forceinline__ void two_sum_merge(double &s, double &c, double s2, d
     c = (c + c2) + e;
 }
 
-// 16 bins per block and 16 groups of workgroup rows per bin: at d = 6,
-// nb = 500 that is 188 blocks, which spread the read of the partials over
-// most of the CUs (32 bins per block left 94 blocks and took 1.6x as long).
-constexpr int kFinBins = 16;                        // bins per histogram block
-constexpr int kFinGroups = kFinThreads / kFinBins;  // workgroup-row groups per bin
+// After pass c.it of a device-steps run: records (I, var), runs
+// Weighted-Estimates over the passes so far and Check-Convergence (the same
+// code and roundings as the host driver), ends the run if it converged or
+// the pass saw a non-finite value, and mirrors all of it to the host.
+__device__ void decide(const RunCtl &c, double I, double V, bool bad) {
+    RunState *st = c.state;
+    const int it = c.it, k = it + 1;
+    c.iters[it] = I;
+    c.iters[c.itmax + it] = V;
+    double est[3] = {st->est[0], st->est[1], st->est[2]};
+    int32_t status = kRunGoing;
+    if (bad) {
+        status = kRunNonFinite;
+    } else {
+        weighted_estimate(k, c.iters, c.iters + c.itmax, est);
+        if (converged_after(k, est, c.tau_rel, c.chi2_max)) status = kRunConverged;
+    }
+    st->k = k;
+    st->status = status;
+    for (int i = 0; i < 3; ++i) st->est[i] = est[i];
+    if (status != kRunGoing) st->last = it;
+    if (c.host) {
+        // everything else first, k last: a host that sees k has the rest
+        c.host_iters[it] = I;
+        c.host_iters[c.itmax + it] = V;
+        c.host->status = status;
+        for (int i = 0; i < 3; ++i) c.host->est[i] = est[i];
+        if (status != kRunGoing) c.host->last = it;
+        __threadfence_system();
+        *(volatile int32_t *)&c.host->k = k;
+        __threadfence_system();
+    }
+}
 
-// Blocks [0, nhb): kFinBins bins per block; for each bin, group q sums the
-// workgroup rows q, q + kFinGroups, ... in order and the groups are merged in
-// order, so the result depends only on the number of workgroups.  Block nhb:
-// the totals, each thread summing a strided subset of workgroups in order,
-// then a fixed pairwise tree.  All merges are TwoSum-compensated.
+// Blocks [0, nhb): kFinThreads bins per block; each thread sums its bin's
+// kHistAcc accumulators in order (TwoSum) into out and clears them for the
+// next pass.  Block nhb: the totals, each thread summing a strided subset of
+// workgroups in order, then a fixed pairwise tree.  All merges are
+// TwoSum-compensated.  In a device-steps run the pass's decision follows,
+// and the whole launch does nothing once the run has ended.
 __global__ void __launch_bounds__(kFinThreads)
-finalize_kernel(const double *__restrict__ part, int blocks, int nhist, int hist_stride, int nhb,
-                uint32_t *flag, double *out) {
+finalize_kernel(const double *__restrict__ part, double *__restrict__ hacc, int blocks, int nhist,
+                int hist_stride, int nhb, uint32_t *flag, double *out, const RunCtl ctl) {
+    // (this launch's own decision can only set last to ctl.it, which keeps
+    // every block of it running)
+    if (ctl.state && ctl.it > ctl.state->last) return;
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < nhb) {
-        __shared__ double gs[kFinGroups][kFinBins], gc[kFinGroups][kFinBins];
-        const int lane = tid % kFinBins, grp = tid / kFinBins;
-        const int b = blockIdx.x * kFinBins + lane;
-        double s = 0.0, c = 0.0;
+        const int b = blockIdx.x * kFinThreads + tid;
         if (b < nhist) {
-            const double *col = part + 4 * (size_t)blocks + b;
-#pragma unroll 4
-            for (int w = grp; w < blocks; w += kFinGroups)
-                two_sum_merge(s, c, col[(size_t)w * hist_stride], 0.0);
-        }
-        gs[grp][lane] = s;
-        gc[grp][lane] = c;
-        __syncthreads();
-        if (grp == 0 && b < nhist) {
-            for (int q = 1; q < kFinGroups; ++q) two_sum_merge(s, c, gs[q][lane], gc[q][lane]);
+            double *acc = hacc + b;
+            double s = 0.0, c = 0.0;
+#pragma unroll
+            for (int x = 0; x < kHistAcc; ++x) {
+                two_sum_merge(s, c, acc[(size_t)x * hist_stride], 0.0);
+                acc[(size_t)x * hist_stride] = 0.0;
+            }
             out[4 + b] = s + c;
         }
         return;
@@ -101,28 +132,44 @@ finalize_kernel(const double *__restrict__ part, int blocks, int nhist, int hist
         __syncthreads();
     }
     if (tid == 0) {
-        out[0] = red[0][0] + red[0][1];
-        out[1] = red[0][2] + red[0][3];
-        out[2] = *flag ? 1.0 : 0.0;
+        const double I = red[0][0] + red[0][1], V = red[0][2] + red[0][3];
+        const bool bad = *flag != 0u;
+        out[0] = I;
+        out[1] = V;
+        out[2] = bad ? 1.0 : 0.0;
         out[3] = 0.0;
         *flag = 0u;
+        if (ctl.state) decide(ctl, I, V, bad);
     }
 }
 
 __global__ void clear_flag_kernel(uint32_t *flag) { *flag = 0u; }
 
+__global__ void zero_kernel(double *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
 }  // namespace
 
-hipError_t launch_finalize(const double *partials, int blocks, int nhist, int hist_stride,
-                           int with_hist, uint32_t *flag, double *out, hipStream_t stream) {
-    const int nhb = with_hist ? (nhist + kFinBins - 1) / kFinBins : 0;
+hipError_t launch_finalize(const double *partials, double *hist_acc, int blocks, int nhist, int hist_stride,
+                           int with_hist, uint32_t *flag, double *out, const RunCtl &ctl,
+                           hipStream_t stream) {
+    const int nhb = with_hist ? (nhist + kFinThreads - 1) / kFinThreads : 0;
     hipLaunchKernelGGL(finalize_kernel, dim3(nhb + 1), dim3(kFinThreads), 0, stream, partials,
-                       blocks, nhist, hist_stride, nhb, flag, out);
+                       hist_acc, blocks, nhist, hist_stride, nhb, flag, out, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_clear_flag(uint32_t *flag, hipStream_t stream) {
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, stream, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 

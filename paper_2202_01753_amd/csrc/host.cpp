@@ -84,6 +84,7 @@ mc_status validate(const mc_problem *pr) {
     if (g > kMaxIntervals) return MC_EINVAL;
     if (pr->precision != MC_FP64 && pr->precision != MC_FP32_EVAL) return MC_EINVAL;
     if (pr->one_d != 0 && pr->one_d != 1) return MC_EINVAL;
+    if (pr->device_steps != 0 && pr->device_steps != 1) return MC_EINVAL;
     if (is_fp32(pr) && g > (int64_t(1) << 24)) return MC_EINVAL;  // digits exact in float
     if (pr->nbins < 2 || pr->nbins > (1 << 20)) return MC_EINVAL;
     if (lds_bytes_of(d, pr->nbins, true, is_fp32(pr)) > kLdsDynamicLimit) return MC_EINVAL;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mcubes.h"
+
 namespace mcubes {
 
 constexpr int kMaxDim = 16;
@@ -19,7 +21,8 @@ constexpr int kBatchMaxDim = 10;     // dimensions the batched kernel supports
 struct SampleArgs {
     const double *grid;     // dim*(nb+1) boundaries, unit coordinates
     const void *tables;     // 2*256*256 of the evaluation precision, or nullptr
-    double *partials;       // per workgroup: 4 totals, then (optional) dim*nb bins
+    double *partials;       // per workgroup 4 totals
+    double *hist_acc;       // kHistAcc histogram accumulators, hist_stride doubles apart
     uint32_t *flag;         // set to nonzero when the integrand is not finite
     double *trace;          // optional per-sample / per-cube records
     int64_t m;              // sub-cubes
@@ -31,7 +34,7 @@ struct SampleArgs {
     int32_t nb;             // bins per axis
     int32_t g;              // intervals per axis
     int32_t hist;           // nonzero: collect bin contributions (V-Sample)
-    int32_t hist_stride;    // doubles between two workgroups' histograms in partials
+    int32_t hist_stride;    // doubles between two histogram accumulators
     int32_t kind;           // integrand id * 32 + dim (dispatch in the batched kernel)
     int32_t one_d;          // nonzero: collect bin contributions of the first axis only
     int32_t hist_copies;    // LDS histogram copies: 2 = lanes 32-63 of a wave add into a second
@@ -43,6 +46,8 @@ struct SampleArgs {
     double inv_pm1;         // 1 / (p - 1)
     double cval;            // constant integrand value
     const void *consts;     // kConstStride values of the evaluation precision per axis
+    const int32_t *run_last;  // nullptr, or the last iteration of a run whose steps run on the
+                              // device: a pass with iter beyond it does nothing
     int32_t sdig[kMaxDim];  // stride in base g, least significant digit first
 };
 
@@ -58,10 +63,70 @@ const void *sample_kernel(int integrand, int dim, bool trace, bool fp32);
 hipError_t launch_sample(int integrand, int dim, int blocks, int threads, size_t lds_bytes,
                          hipStream_t stream, const SampleArgs &args);
 
-// Reduces per-workgroup partials in a fixed order into out = [I, var, flag, 0, hist...]
-// and clears the flag.
-hipError_t launch_finalize(const double *partials, int blocks, int nhist, int hist_stride,
-                           int with_hist, uint32_t *flag, double *out, hipStream_t stream);
+// Histogram accumulators of a V-Sample pass (a region of their own, so that
+// the totals of a pass with more workgroups never reach them): workgroup b adds its LDS histogram into accumulator b % kHistAcc
+// with device-scope FP64 atomics.  Eight copies cut the atomics that meet on
+// one address eightfold (workgroups are dispatched round-robin over the
+// chip's eight XCDs, so the copies also split by XCD); the finalize sums them
+// in order.
+constexpr int kHistAcc = 8;
+
+// Reduces the per-workgroup totals in a fixed order and sums the histogram
+// accumulators in order into out = [I, var, flag, 0, hist...]; clears the
+// accumulators (for the next pass) and the flag.
+// A run whose steps between sampling passes (Weighted-Estimates,
+// Check-Convergence, Adjust-Bin-Bounds of Alg. 2) run on the device: its
+// state in the workspace, mirrored after every pass into page-locked host
+// memory that the host reads once the pass is over.  last is the index of
+// the run's last iteration: itmax - 1 until a pass ends the run earlier
+// (converged, or a non-finite value); every kernel of a later pass then does
+// nothing.
+struct RunState {
+    int32_t last;
+    int32_t status;   // kRunGoing, kRunConverged or kRunNonFinite
+    int32_t k;        // passes finished
+    int32_t pad;
+    double est[3];    // weighted estimate, its standard deviation, chi^2/dof after k passes
+    double pad2;
+};
+constexpr int32_t kRunGoing = 0, kRunConverged = 1, kRunNonFinite = 2;
+
+// The decision the finalize takes after pass it of such a run (state null:
+// none, the host takes it).  iters holds I_0 .. I_{itmax-1}, then var_0 ..
+// var_{itmax-1}, on the device; host_iters the same in the host mirror.
+struct RunCtl {
+    RunState *state;
+    double *iters;
+    RunState *host;
+    double *host_iters;
+    int32_t it, itmax;
+    double tau_rel, chi2_max;
+};
+
+hipError_t launch_finalize(const double *partials, double *hist_acc, int blocks, int nhist, int hist_stride,
+                           int with_hist, uint32_t *flag, double *out, const RunCtl &ctl,
+                           hipStream_t stream);
+
+// Start of a device-steps run: the state (last = itmax - 1, nothing done) and
+// Init-Bins (boundaries i/nb on every axis) in the workspace, and in
+// host_grid (mapped host memory) unless it is null.
+hipError_t launch_run_init(RunState *state, double *grid, double *host_grid, int d, int nb, int itmax,
+                           hipStream_t stream);
+
+// Adjust-Bin-Bounds on the device after pass it of a device-steps run (nothing
+// if the run ended before it): one workgroup per axis (m-Cubes1D: axis 0, then
+// copied to every axis), the host's steps with sums in a fixed order of its
+// own and the device library's pow and log: the host's result to rounding.  Reads the histogram hist (d*nb), rewrites grid in place.
+// last may be null (no run: always adjusts).
+// host_grid (mapped host memory), unless null, receives the same boundaries.
+hipError_t launch_refine(double *grid, double *host_grid, const double *hist, int d, int nb, int one_d,
+                         double alpha, const int32_t *last, int it, hipStream_t stream);
+// LDS of one refinement workgroup, and the largest nb it takes.
+size_t refine_lds_bytes(int nb);
+constexpr int kDeviceStepsMaxBins = MC_DEVICE_STEPS_MAX_BINS;
+
+// Zeroes n doubles (the histogram accumulators, before a workspace's first pass).
+hipError_t launch_zero(double *p, size_t n, hipStream_t stream);
 
 hipError_t launch_clear_flag(uint32_t *flag, hipStream_t stream);
 

@@ -35,9 +35,9 @@ struct Geometry {
     int threads;
     int blocks_adj, blocks_noadj;
     size_t lds_adj, lds_noadj;
-    int hist_stride;          // doubles per workgroup histogram (padded)
+    int hist_stride;          // doubles per histogram accumulator (padded)
     int hist_copies;          // LDS histogram copies in adjusting passes (1 or 2)
-    size_t off_consts, off_grid, off_tables, off_partials, off_out, off_flag, total;
+    size_t off_consts, off_grid, off_tables, off_partials, off_hist, off_out, off_flag, off_run, total;
 };
 
 mc_status blocks_for(const void *fn, int threads, size_t lds, int64_t m, int requested, int *out) {
@@ -73,7 +73,7 @@ mc_status blocks_for(const void *fn, int threads, size_t lds, int64_t m, int req
 // the same number of every workgroup's waves), the one that keeps the most
 // waves resident per CU given the kernel's registers and the adjusting pass's
 // LDS; on a tie the larger, which means fewer workgroups and so fewer
-// histogram partials to merge.  768 is the d = 8 case: two 64 KB workgroups
+// histogram flushes.  768 is the d = 8 case: two 64 KB workgroups
 // of 12 waves fit where one of 16 did.
 mc_status pick_threads(const void *fn, size_t lds, int *out) {
     HIP_TRY(allow_lds(fn, lds));
@@ -132,7 +132,7 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     st = blocks_for(fn, G.threads, G.lds_noadj, G.m, pr->blocks, &G.blocks_noadj);
     if (st != MC_OK) return st;
     G.hist_stride = (int)((d * (size_t)nb + 31) / 32 * 32);
-    const size_t part_adj = (4 + (size_t)G.hist_stride) * G.blocks_adj;
+    const size_t part_adj = 4 * (size_t)G.blocks_adj;
     const size_t part_noadj = 4 * (size_t)G.blocks_noadj;
     size_t off = 0;
     const size_t real = f32 ? sizeof(float) : sizeof(double);
@@ -144,10 +144,17 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     if (pr->integrand == MC_F_GAUSS_TABLES) off = align_up(off + real * kTablesLen);
     G.off_partials = off;
     off = align_up(off + sizeof(double) * std::max(part_adj, part_noadj));
+    // the kHistAcc histogram accumulators of adjusting passes, kept zero
+    // between passes
+    G.off_hist = off;
+    off = align_up(off + sizeof(double) * kHistAcc * (size_t)G.hist_stride);
     G.off_out = off;
     off = align_up(off + sizeof(double) * (4 + (size_t)d * nb));
     G.off_flag = off;
     off = align_up(off + sizeof(uint32_t));
+    // a device-steps run's state and its per-iteration (I, var)
+    G.off_run = off;
+    off = align_up(off + sizeof(RunState) + sizeof(double) * 2 * (size_t)pr->itmax);
     G.total = off;
     *geo = G;
     return MC_OK;
@@ -161,6 +168,7 @@ void fill_args(const mc_problem *pr, const Geometry &G, char *ws, uint32_t iter,
     const void *tables = pr->integrand == MC_F_GAUSS_TABLES ? ws + G.off_tables : nullptr;
     sample_args(pr, G.g, G.m, G.p, iter, adjust, ws + G.off_consts, grid, tables, a);
     a->partials = reinterpret_cast<double *>(ws + G.off_partials);
+    a->hist_acc = reinterpret_cast<double *>(ws + G.off_hist);
     a->flag = reinterpret_cast<uint32_t *>(ws + G.off_flag);
     a->stride = (int64_t)blocks * G.threads;
     a->hist_stride = G.hist_stride;
@@ -246,8 +254,8 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     HIP_TRY(launch_sample(pr->integrand, d, blocks, G.threads, lds, stream, a));
     if (ev) HIP_TRY(hipEventRecord(ev->e[1], stream));
     double *out_dev = reinterpret_cast<double *>(ws + G.off_out);
-    HIP_TRY(launch_finalize(a.partials, blocks, d * nb, G.hist_stride, adjust ? 1 : 0, a.flag,
-                            out_dev, stream));
+    HIP_TRY(launch_finalize(a.partials, a.hist_acc, blocks, d * nb, G.hist_stride, adjust ? 1 : 0, a.flag,
+                            out_dev, RunCtl{}, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[2], stream));
     if (adjust && d > 1 && !pr->one_d) AxisPool::get().prime(spin_us);
     HIP_TRY(hipMemcpyAsync(out_stage, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
@@ -285,6 +293,10 @@ mc_status prepare(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t
                                    hipMemcpyHostToDevice, stream));
     }
     HIP_TRY(launch_clear_flag(reinterpret_cast<uint32_t *>(ws + G.off_flag), stream));
+    // the histogram accumulators start at zero; each adjusting pass's finalize
+    // clears them again after reading them
+    HIP_TRY(launch_zero(reinterpret_cast<double *>(ws + G.off_hist),
+                        (size_t)kHistAcc * G.hist_stride, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return MC_OK;
 }
@@ -388,6 +400,16 @@ mc_status mc_refine_grid_1d(int32_t dim, int32_t nbins, double alpha, const doub
     return MC_OK;
 }
 
+mc_status mc_refine_grid_device(int32_t dim, int32_t nbins, double alpha, int32_t one_d,
+                                const double *d_hist, double *d_grid, void *stream) {
+    if (dim < 1 || dim > MC_MAX_DIM || nbins < 2 || nbins > kDeviceStepsMaxBins ||
+        !(alpha > 0.0) || !std::isfinite(alpha) || (one_d != 0 && one_d != 1) || !d_hist || !d_grid)
+        return MC_EINVAL;
+    HIP_TRY(launch_refine(d_grid, nullptr, d_hist, dim, nbins, one_d, alpha, nullptr, 0,
+                          static_cast<hipStream_t>(stream)));
+    return MC_OK;
+}
+
 mc_status mc_init_grid(int32_t dim, int32_t nbins, double *h_grid) {
     if (dim < 1 || dim > MC_MAX_DIM || nbins < 2 || !h_grid) return MC_EINVAL;
     init_grid(dim, nbins, h_grid);
@@ -403,6 +425,204 @@ mc_status mc_weighted_estimate(int32_t k, const double *h_I, const double *h_var
 }  // extern "C"
 
 namespace {
+
+// The calling thread's page-locked host mirror of a device-steps run, mapped
+// for the device (bytes, grown on demand and kept until the process ends):
+// its RunState, then 2 * itmax doubles of per-iteration results, then the
+// grid.
+hipError_t run_mirror(size_t bytes, char **host, char **dev) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) {
+            const hipError_t e = hipHostFree(buf);
+            buf = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
+        const size_t want = std::max(bytes, size_t(1) << 16);
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&buf), want,
+                                           hipHostMallocMapped | hipHostMallocPortable |
+                                               hipHostMallocCoherent);
+        if (e != hipSuccess) return e;
+        cap = want;
+    }
+    void *d = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(&d, buf, 0);
+    if (e != hipSuccess) return e;
+    *host = buf;
+    *dev = static_cast<char *>(d);
+    return hipSuccess;
+}
+
+// The calling thread's markers for timed device-steps runs on the current
+// device, created once (and again after a change of device) and kept until
+// the process ends.  Per pass two: after the sampling kernel, and "done"
+// after the pass's last kernel.  Three slots each, since the next passes are
+// queued before a pass is read.
+struct RunEvents {
+    int device = -1;
+    hipEvent_t start = nullptr, sampled[3] = {}, done[3] = {};
+};
+
+hipError_t run_events(RunEvents **out) {
+    thread_local RunEvents ev;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (ev.device != dev) {
+        hipEvent_t *all[] = {&ev.start, &ev.sampled[0], &ev.sampled[1], &ev.sampled[2],
+                             &ev.done[0], &ev.done[1], &ev.done[2]};
+        for (hipEvent_t *x : all)
+            if (*x) {
+                (void)hipEventDestroy(*x);
+                *x = nullptr;
+            }
+        ev.device = -1;
+        for (hipEvent_t *x : all)
+            if ((e = hipEventCreate(x)) != hipSuccess) return e;
+        ev.device = dev;
+    }
+    *out = &ev;
+    return hipSuccess;
+}
+
+// Alg. 2 with its steps between passes on the device: Init-Bins and the run
+// state, then per pass the sampling kernel, the finalize (totals, histogram,
+// Weighted-Estimates, Check-Convergence) and, while adjusting, the bin
+// adjustment, all on the stream.  The sampling kernel of the next pass is
+// always queued before the host waits for a pass, so the device never waits
+// for the host; the rest of that pass is queued once the decision of the
+// pass before is known, so a run that converges leaves only one sampling
+// launch queued behind it, which does nothing.  The decisions, the
+// per-iteration results and the grid come back through the mapped mirror.
+mc_status integrate_device(const mc_problem *prob, const Geometry &G, char *ws, hipStream_t s,
+                           mc_result *out, double *h_iters, double *h_grid, mc_timing *timing) {
+    const int d = prob->dim, nb = prob->nbins, itmax = prob->itmax;
+    const size_t grid_len = (size_t)d * (nb + 1);
+    char *hbuf = nullptr, *dbuf = nullptr;
+    HIP_TRY(run_mirror(sizeof(RunState) + sizeof(double) * (2 * (size_t)itmax + grid_len), &hbuf, &dbuf));
+    RunEvents *ev = nullptr;
+    if (timing) HIP_TRY(run_events(&ev));
+    RunState *hm = reinterpret_cast<RunState *>(hbuf), *hm_dev = reinterpret_cast<RunState *>(dbuf);
+    double *h_its = reinterpret_cast<double *>(hm + 1), *h_its_dev = reinterpret_cast<double *>(hm_dev + 1);
+    double *h_gr = h_its + 2 * (size_t)itmax, *h_gr_dev = h_its_dev + 2 * (size_t)itmax;
+    double *mirror_grid = h_grid ? h_gr_dev : nullptr;
+    std::memset(static_cast<void *>(hm), 0, sizeof(RunState));
+    hm->last = itmax - 1;
+    RunState *dst = reinterpret_cast<RunState *>(ws + G.off_run);
+    double *iters = reinterpret_cast<double *>(dst + 1);
+    double *grid = reinterpret_cast<double *>(ws + G.off_grid);
+    double *out_dev = reinterpret_cast<double *>(ws + G.off_out);
+    double *partials = reinterpret_cast<double *>(ws + G.off_partials);
+    double *hist_acc = reinterpret_cast<double *>(ws + G.off_hist);
+    uint32_t *flag = reinterpret_cast<uint32_t *>(ws + G.off_flag);
+    hipEvent_t *done = timing ? ev->done : nullptr;
+    const void *fn = sample_kernel(prob->integrand, d, false, is_fp32(prob));
+    auto pass_blocks = [&](int it) { return it < prob->ita ? G.blocks_adj : G.blocks_noadj; };
+    // the sampling kernel of pass it (and its marker)
+    auto head = [&](int it) -> hipError_t {
+        const bool adjust = it < prob->ita;
+        const size_t lds = adjust ? G.lds_adj : G.lds_noadj;
+        SampleArgs a;
+        fill_args(prob, G, ws, (uint32_t)it, adjust, pass_blocks(it), &a);
+        a.run_last = &dst->last;
+        hipError_t e;
+        if (timing && it == 0 && (e = hipEventRecord(ev->start, s)) != hipSuccess) return e;
+        if ((e = allow_lds(fn, lds)) != hipSuccess) return e;
+        if ((e = launch_sample(prob->integrand, d, pass_blocks(it), G.threads, lds, s, a)) != hipSuccess)
+            return e;
+        return timing ? hipEventRecord(ev->sampled[it % 3], s) : hipSuccess;
+    };
+    // the rest of pass it: finalize and decision, bin adjustment, done marker
+    auto tail = [&](int it) -> hipError_t {
+        const bool adjust = it < prob->ita;
+        const RunCtl ctl{dst, iters, hm_dev, h_its_dev, it, itmax, prob->tau_rel, prob->chi2_max};
+        hipError_t e = launch_finalize(partials, hist_acc, pass_blocks(it), d * nb, G.hist_stride,
+                                       adjust ? 1 : 0, flag, out_dev, ctl, s);
+        if (e != hipSuccess) return e;
+        if (adjust && (e = launch_refine(grid, mirror_grid, out_dev + 4, d, nb, prob->one_d, prob->alpha,
+                                         &dst->last, it, s)) != hipSuccess)
+            return e;
+        return timing ? hipEventRecord(done[it % 3], s) : hipSuccess;
+    };
+    // until pass it's decision is in the mirror: with timing, the pass's done
+    // marker; otherwise the mirror's pass count, which the finalize writes
+    // last (no marker, which would hold the stream for a few microseconds),
+    // with a look at the stream now and then, so that an error or a stream
+    // that has run dry ends the wait
+    auto wait_pass = [&](int it) -> hipError_t {
+        if (timing) return hipEventSynchronize(done[it % 3]);
+        const volatile int32_t *kk = &reinterpret_cast<volatile RunState *>(hm)->k;
+        for (unsigned spin = 1;; ++spin) {
+            if (*kk > it) break;
+            if (spin % 1024 == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipSuccess && *kk <= it) return hipErrorUnknown;  // drained, no decision
+                if (q != hipSuccess && q != hipErrorNotReady) return q;
+            }
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+        return hipSuccess;
+    };
+    double ms_s = 0.0, ms_f = 0.0;
+    int k = 0;
+    hipError_t err = launch_run_init(dst, grid, mirror_grid, d, nb, itmax, s);
+    if (err == hipSuccess) err = head(0);
+    if (err == hipSuccess) err = tail(0);
+    if (err == hipSuccess && itmax > 1) err = head(1);
+    for (int it = 0; err == hipSuccess && it < itmax; ++it) {
+        if ((err = wait_pass(it)) != hipSuccess) break;
+        k = it + 1;
+        if (timing) {
+            float a_ms = 0.f, b_ms = 0.f;
+            hipEvent_t from = it == 0 ? ev->start : done[(it - 1) % 3];
+            if ((err = hipEventElapsedTime(&a_ms, from, ev->sampled[it % 3])) != hipSuccess ||
+                (err = hipEventElapsedTime(&b_ms, ev->sampled[it % 3], done[it % 3])) != hipSuccess)
+                break;
+            ms_s += a_ms;
+            ms_f += b_ms;
+        }
+        if (reinterpret_cast<volatile RunState *>(hm)->last <= it) break;  // pass it ended the run
+        // the run goes on: the rest of pass it + 1, whose sampling kernel is
+        // running, and the sampling kernel after it
+        if ((err = tail(it + 1)) != hipSuccess) break;
+        if (it + 2 < itmax && (err = head(it + 2)) != hipSuccess) break;
+    }
+    // a sampling launch queued after the last pass does nothing; wait for it too
+    const hipError_t err2 = hipStreamSynchronize(s);
+    HIP_TRY(err);
+    HIP_TRY(err2);
+    const volatile RunState *v = hm;
+    if (v->status == kRunNonFinite) return MC_ENONFINITE;
+    if (h_grid) std::memcpy(h_grid, h_gr, sizeof(double) * grid_len);
+    out->estimate = v->est[0];
+    out->error = v->est[1];
+    out->chi2_dof = v->est[2];
+    out->iterations = k;
+    out->converged = v->status == kRunConverged ? 1 : 0;
+    out->calls = (int64_t)k * G.m * G.p;
+    if (h_iters)
+        for (int i = 0; i < k; ++i) {
+            h_iters[2 * i] = h_its[i];
+            h_iters[2 * i + 1] = h_its[itmax + i];
+        }
+    if (timing) {
+        timing->sample_ms = ms_s;
+        timing->finalize_ms = ms_f;
+        timing->launches = k;
+        timing->blocks = prob->ita > 0 ? G.blocks_adj : G.blocks_noadj;
+        timing->threads = G.threads;
+        timing->lds_bytes = (int32_t)(prob->ita > 0 ? G.lds_adj : G.lds_noadj);
+    }
+    return MC_OK;
+}
+
+// Whether a run keeps the steps between passes on the device: asked for, and
+// the bin adjustment's LDS holds nb.
+bool steps_on_device(const mc_problem *prob) {
+    return prob->device_steps == 1 && prob->nbins <= kDeviceStepsMaxBins;
+}
 
 // Alg. 2 on a workspace; upload: copy the constants and tables first
 // (otherwise a previous mc_prepare() of the same problem left them there).
@@ -420,6 +640,7 @@ mc_status integrate(const mc_problem *prob, void *d_ws, size_t ws_bytes, void *s
         st = prepare(prob, G, ws, s);
         if (st != MC_OK) return st;
     }
+    if (pinned && steps_on_device(prob)) return integrate_device(prob, G, ws, s, out, h_iters, h_grid, timing);
 
     const int d = prob->dim, nb = prob->nbins;
     std::vector<double> grid((size_t)d * (nb + 1)), buf(4 + (size_t)d * nb);

@@ -14,8 +14,9 @@
 //   -> (V-Sample only) I_k^2 added to one LDS bin per axis.
 // Per sub-cube: I_t and the unbiased variance estimate, accumulated per lane
 // with error-free transformations.  Per workgroup: a fixed-order wave and
-// workgroup reduction, then the totals and the LDS histogram go to this
-// workgroup's slot of the partials array for the finalize kernel.
+// workgroup reduction, then the totals go to this workgroup's slot of the
+// partials array and the LDS histogram is added into one of the histogram
+// accumulators, both for the finalize kernel.
 #pragma once
 
 #include <type_traits>
@@ -636,6 +637,7 @@ __global__ void __launch_bounds__(kMaxBlock)
     __attribute__((amdgpu_waves_per_eu(kFixedWaves<F, D, TRACE, F32> ? kFixedWaves<F, D, TRACE, F32> : 1,
                                        kFixedWaves<F, D, TRACE, F32> ? kFixedWaves<F, D, TRACE, F32> : 8)))
     vsample_kernel(const SampleArgs a) {
+    if (a.run_last && (int64_t)a.iter > (int64_t)*a.run_last) return;  // the run has ended
     extern __shared__ double lds[];
     const LdsView<F32> v(lds, D, a.nb);
     load_lds<D, F32>(a, v);
@@ -675,12 +677,14 @@ __global__ void __launch_bounds__(kMaxBlock)
     }
     block_totals(sI, cI, sV, cV, bad, a.partials + 4 * (size_t)blockIdx.x, a.flag);
     if (a.hist) {
-        double *ph = a.partials + 4 * (size_t)gridDim.x + (size_t)blockIdx.x * a.hist_stride;
+        // into accumulator blockIdx % kHistAcc (ordinary device memory, so the
+        // hardware FP64 atomic add applies); bins it never reached are skipped
         const int n = D * a.nb;
-        if (a.hist_copies > 1)
-            for (int i = threadIdx.x; i < n; i += blockDim.x) ph[i] = v.hist[i] + v.hist[n + i];
-        else
-            for (int i = threadIdx.x; i < n; i += blockDim.x) ph[i] = v.hist[i];
+        double *acc = a.hist_acc + (size_t)(blockIdx.x % kHistAcc) * a.hist_stride;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const double h = a.hist_copies > 1 ? v.hist[i] + v.hist[n + i] : v.hist[i];
+            if (h != 0.0) unsafeAtomicAdd(acc + i, h);
+        }
     }
 }
 

@@ -21,8 +21,11 @@ LIBRARY = os.path.join(PKG, "libmcubes.so")
 OK, EINVAL, EWORKSPACE, ENONFINITE, EDEVICE = 0, 1, 2, 3, 4
 INTEGRANDS = {"const": 0, "gauss_product": 1, "corner_peak": 2, "gauss_tables": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+MC_MAX_DIM = 16
+MC_DEVICE_STEPS_MAX_BINS = 4000  # bins per axis up to which device_steps keeps the steps on the device
 EXPORTS = ("mc_status_string", "mc_shape", "mc_workspace_bytes", "mc_launch_shape", "mc_prepare",
-           "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_init_grid",
+           "mc_sample_iteration", "mc_refine_grid", "mc_refine_grid_1d", "mc_refine_grid_device",
+           "mc_init_grid",
            "mc_weighted_estimate", "mc_integrate", "mc_integrate_prepared", "mc_integrate_noalloc",
            "mc_batch_workspace_bytes", "mc_batch_integrate", "mc_server_create",
            "mc_server_set_step_budget", "mc_server_submit", "mc_server_step", "mc_server_poll", "mc_server_finished",
@@ -58,6 +61,7 @@ class Problem(C.Structure):
         ("threads", C.c_int32),
         ("one_d", C.c_int32),
         ("chi2_max", C.c_double),
+        ("device_steps", C.c_int32),
     ]
 
 
@@ -101,6 +105,8 @@ def lib() -> C.CDLL:
                                      C.c_int64, C.c_int64], C.c_int32),
             "mc_refine_grid": ([C.c_int32, C.c_int32, C.c_double, dp, dp], C.c_int32),
             "mc_refine_grid_1d": ([C.c_int32, C.c_int32, C.c_double, dp, dp], C.c_int32),
+            "mc_refine_grid_device": ([C.c_int32, C.c_int32, C.c_double, C.c_int32, vp, vp, vp],
+                                      C.c_int32),
             "mc_init_grid": ([C.c_int32, C.c_int32, dp], C.c_int32),
             "mc_weighted_estimate": ([C.c_int32, dp, dp, dp], C.c_int32),
             "mc_integrate": ([P, vp, sz, vp, C.POINTER(Result), dp, dp, C.POINTER(Timing)],
@@ -166,7 +172,8 @@ class BoundProblem:
             precision=PRECISIONS[prob.get("precision", "fp64")],
             alpha=float(prob["alpha"]), tau_rel=float(prob.get("tau_rel", 0.0)),
             seed=int(prob["seed"]) & (2**64 - 1), blocks=int(blocks), threads=int(threads),
-            one_d=1 if prob.get("one_d", False) else 0, chi2_max=float(prob.get("chi2_max", 0.0)))
+            one_d=1 if prob.get("one_d", False) else 0, chi2_max=float(prob.get("chi2_max", 0.0)),
+            device_steps=1 if prob.get("device_steps", False) else 0)
 
     @property
     def ref(self):
@@ -205,6 +212,21 @@ def refine_grid_1d(dim: int, nbins: int, alpha: float, hist, grid):
     h = _f64(hist)
     _check(lib().mc_refine_grid_1d(dim, nbins, alpha, _dp(h), _dp(out)), "mc_refine_grid_1d")
     return out
+
+
+def refine_grid_device(dim: int, nbins: int, alpha: float, hist, grid, one_d: bool = False,
+                       stream=None):
+    """mc_refine_grid_device on copies of hist and grid in device memory;
+    returns the adjusted grid (host)."""
+    torch = _torch()
+    h = torch.from_numpy(_f64(hist).copy()).to("cuda")
+    g = torch.from_numpy(_f64(grid).copy()).to("cuda")
+    torch.cuda.synchronize()
+    _check(lib().mc_refine_grid_device(dim, nbins, alpha, 1 if one_d else 0, C.c_void_p(h.data_ptr()),
+                                       C.c_void_p(g.data_ptr()), _stream(stream)),
+           "mc_refine_grid_device")
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
 
 
 def init_grid(dim: int, nbins: int):

@@ -27,7 +27,8 @@ TABLE_N = 256
 
 
 def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=None, hi=None,
-             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64", one_d=False, chi2_max=0.0):
+             ita=None, alpha=1.5, tau_rel=0.0, seed=0, precision="fp64", one_d=False, chi2_max=0.0,
+             device_steps=False):
     return {
         "integrand": integrand,
         "params": np.ascontiguousarray(params, dtype=np.float64),
@@ -45,6 +46,7 @@ def _problem(integrand, params, dim, maxcalls, nbins, itmax, *, tables=None, lo=
         "precision": precision,
         "one_d": bool(one_d),
         "chi2_max": float(chi2_max),
+        "device_steps": bool(device_steps),
     }
 
 

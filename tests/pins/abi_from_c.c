@@ -22,7 +22,8 @@ int main(void) {
     const entry_fn entry[] = {
         (entry_fn)mc_status_string, (entry_fn)mc_shape, (entry_fn)mc_workspace_bytes,
         (entry_fn)mc_launch_shape, (entry_fn)mc_prepare, (entry_fn)mc_sample_iteration,
-        (entry_fn)mc_refine_grid, (entry_fn)mc_refine_grid_1d, (entry_fn)mc_init_grid,
+        (entry_fn)mc_refine_grid, (entry_fn)mc_refine_grid_1d, (entry_fn)mc_refine_grid_device,
+        (entry_fn)mc_init_grid,
         (entry_fn)mc_weighted_estimate, (entry_fn)mc_integrate, (entry_fn)mc_integrate_prepared,
         (entry_fn)mc_integrate_noalloc, (entry_fn)mc_batch_workspace_bytes,
         (entry_fn)mc_batch_integrate, (entry_fn)mc_server_create, (entry_fn)mc_server_submit,

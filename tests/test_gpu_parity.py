@@ -533,6 +533,28 @@ def _production_passes(prob, grids, noadjust=True):
         _compare_totals(gpu, ref, _positive_scale(ref), f"no-adjust iter {it}", tol)
 
 
+@pytest.mark.parametrize("precision,threads", [("fp64", 256), ("fp32", 0)])
+def test_no_adjust_pass_with_more_workgroups_between_adjusting_passes(precision, threads):
+    """d = 2, nb = 4000: the adjusting pass's LDS (grid and histogram, 128 KB)
+    fits one workgroup per CU, the no-adjust pass's (the grid, 64 KB) more, so
+    the no-adjust pass launches more workgroups and writes more per-workgroup
+    totals.  The histogram accumulators that the adjusting passes add into
+    must come through it untouched: adjusting, no-adjust, adjusting on one
+    workspace, each against the oracle."""
+    prob = W.corner_peak(2, 21, maxcalls=4_000_000, nbins=4000, itmax=3, precision=precision)
+    s = M.Sampler(prob, threads=threads)
+    b_adj = M.launch_shape(s.bp, adjust=True)[0]
+    b_noadj = M.launch_shape(s.bp, adjust=False)[0]
+    print(precision, "blocks adjusting", b_adj, "no-adjust", b_noadj, flush=True)
+    assert b_noadj > b_adj
+    grid = _random_grid(2, 4000, 23)
+    for it, adjust in enumerate([True, False, True]):
+        gpu = s.sample(it, grid, adjust)
+        gpu["nbins"] = 4000
+        ref = O.vsample(prob, it, grid, hist=adjust)
+        _compare_totals(gpu, ref, _positive_scale(ref), f"pass {it} adjust={adjust}", _tol(prob))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_production_tables_d6(precision):
     # FP32 evaluation runs 1024 x 768 lanes (two workgroups per CU, launched

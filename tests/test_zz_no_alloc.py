@@ -37,10 +37,12 @@ def test_noalloc_matches_integrate_on_successive_calls():
 
 
 def test_noalloc_rejects_problems_beyond_the_scratch():
-    # d = 8 at 1e9 samples: 2048 workgroups' histogram partials alone are 65 MB
+    # 2^20 workgroups asked for: their totals alone are 32 MB
     prob = W.config_corner8(seed=1)
-    bp = M.BoundProblem(prob)
+    bp = M.BoundProblem(prob, 1 << 20)
     assert M.workspace_bytes(bp) > 16 << 20
+    # the benchmark's own d = 8 shape fits
+    assert M.workspace_bytes(M.BoundProblem(prob)) < 16 << 20
     res = M.Result(estimate=-3.0)
     code = M.lib().mc_integrate_noalloc(bp.ref, None, C.byref(res), None, None)
     assert code == M.EWORKSPACE and res.estimate == -3.0
