@@ -143,6 +143,18 @@ void init_grid(int d, int nb, double *grid) {
     }
 }
 
+void tables_f32(const double *tables, float *out) {
+    for (int t = 0; t < 2; ++t) {
+        const double *T = tables + (size_t)t * kTableN * kTableN;
+        float *P = out + (size_t)t * 2 * kTableN * kTableN;
+        for (int a = 0; a < kTableN; ++a)
+            for (int b = 0; b < kTableN; ++b) {
+                P[2 * (a * kTableN + b)] = (float)T[a * kTableN + b];
+                P[2 * (a * kTableN + b) + 1] = a + 1 < kTableN ? (float)T[(a + 1) * kTableN + b] : 0.0f;
+            }
+    }
+}
+
 // Bin adjustment of one axis; returns without change when the contributions
 // carry no usable weight.
 void refine_axis(int nb, double alpha, const double *C, double *B, std::vector<double> &sm,

@@ -26,6 +26,8 @@ constexpr size_t kLdsLimit = 160 * 1024;   // gfx950 LDS per workgroup
 // reserve for the kernels' static arrays (the reduction scratch, 520 bytes).
 constexpr size_t kLdsDynamicLimit = kLdsLimit - 1024;
 constexpr int64_t kTablesLen = 2 * kTableN * kTableN;
+// floats of the two tables in the FP32-eval device layout (row pairs)
+constexpr int64_t kTablesLen32 = 2 * kTablesLen;
 constexpr int64_t kMaxIntervals = int64_t(1) << 30;  // g; keeps digit arithmetic in 32 bits
 
 // On failure the runtime's last-error state is cleared as well, so that the
@@ -60,6 +62,9 @@ void sample_args(const mc_problem *pr, int64_t g, int64_t m, int64_t p, uint32_t
                  const void *consts, const double *grid, const void *tables, SampleArgs *a);
 // Init-Bins: nb equal bins per axis.
 void init_grid(int d, int nb, double *grid);
+// The two tables (kTablesLen doubles, row-major) in the FP32-eval device
+// layout: kTablesLen32 floats, each value rounded once.
+void tables_f32(const double *tables, float *out);
 // Adjust-Bin-Bounds of one axis (scratch vectors of nb, nb, nb+1 doubles).
 void refine_axis(int nb, double alpha, const double *C, double *B, std::vector<double> &sm,
                  std::vector<double> &r, std::vector<double> &prev);

@@ -20,7 +20,8 @@ constexpr int kBatchMaxDim = 10;     // dimensions the batched kernel supports
 // constants arrive in scalar registers.
 struct SampleArgs {
     const double *grid;     // dim*(nb+1) boundaries, unit coordinates
-    const void *tables;     // 2*256*256 of the evaluation precision, or nullptr
+    const void *tables;     // the two tables in the device layout of the evaluation precision
+                            // (see table_cell), or nullptr
     double *partials;       // per workgroup 4 totals
     double *hist_acc;       // kHistAcc histogram accumulators, hist_stride doubles apart
     uint32_t *flag;         // set to nonzero when the integrand is not finite

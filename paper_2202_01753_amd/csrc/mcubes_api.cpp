@@ -141,7 +141,7 @@ mc_status geometry(const mc_problem *pr, Geometry *geo) {
     G.off_grid = off;
     off = align_up(off + sizeof(double) * d * (nb + 1));
     G.off_tables = off;
-    if (pr->integrand == MC_F_GAUSS_TABLES) off = align_up(off + real * kTablesLen);
+    if (pr->integrand == MC_F_GAUSS_TABLES) off = align_up(off + real * (f32 ? kTablesLen32 : kTablesLen));
     G.off_partials = off;
     off = align_up(off + sizeof(double) * std::max(part_adj, part_noadj));
     // the kHistAcc histogram accumulators of adjusting passes, kept zero
@@ -279,8 +279,9 @@ mc_status prepare(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t
         HIP_TRY(hipMemcpyAsync(ws + G.off_consts, c32.data(), sizeof(float) * c32.size(),
                                hipMemcpyHostToDevice, stream));
         if (pr->integrand == MC_F_GAUSS_TABLES) {
-            const std::vector<float> t32(pr->tables, pr->tables + kTablesLen);
-            HIP_TRY(hipMemcpyAsync(ws + G.off_tables, t32.data(), sizeof(float) * kTablesLen,
+            std::vector<float> t32(kTablesLen32);
+            tables_f32(pr->tables, t32.data());
+            HIP_TRY(hipMemcpyAsync(ws + G.off_tables, t32.data(), sizeof(float) * kTablesLen32,
                                    hipMemcpyHostToDevice, stream));
             HIP_TRY(hipStreamSynchronize(stream));  // t32 is about to go out of scope
         }

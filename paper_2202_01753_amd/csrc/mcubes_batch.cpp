@@ -130,7 +130,7 @@ size_t block_layout(const Request &r, size_t *o_consts, size_t *o_tables, size_t
     *o_consts = off;
     off = align_up(off + real * kConstStride * d);
     *o_tables = off;
-    if (r.prob.integrand == MC_F_GAUSS_TABLES) off = align_up(off + real * 2 * kTableN * kTableN);
+    if (r.prob.integrand == MC_F_GAUSS_TABLES) off = align_up(off + real * (fp32_of(r) ? kTablesLen32 : kTablesLen));
     *o_grid0 = off;
     off = align_up(off + sizeof(double) * d * (nb + 1));
     *o_grid1 = off;
@@ -425,7 +425,7 @@ struct mc_server {
         size_t tab_bytes = 0;
         for (size_t k = first_new; k < admitted.size(); ++k)
             if (!admitted[k]->tables.empty())
-                tab_bytes += align_up((fp32_of(*admitted[k]) ? sizeof(float) : sizeof(double)) * kTablesLen);
+                tab_bytes += align_up(fp32_of(*admitted[k]) ? sizeof(float) * kTablesLen32 : sizeof(double) * kTablesLen);
         if (tab_bytes) {
             // this step's copy of the staging buffer: its last copies were two
             // steps ago, which the previous call has waited for
@@ -438,9 +438,8 @@ struct mc_server {
                 char *dst = tab.data() + off;
                 size_t bytes;
                 if (fp32_of(*r)) {
-                    float *f = reinterpret_cast<float *>(dst);
-                    for (size_t i = 0; i < kTablesLen; ++i) f[i] = (float)r->tables[i];
-                    bytes = sizeof(float) * kTablesLen;
+                    tables_f32(r->tables.data(), reinterpret_cast<float *>(dst));
+                    bytes = sizeof(float) * kTablesLen32;
                 } else {
                     std::memcpy(dst, r->tables.data(), sizeof(double) * kTablesLen);
                     bytes = sizeof(double) * kTablesLen;

@@ -135,6 +135,15 @@ struct TableCell {
     R t00, t01, t10, t11, tx, ty;
 };
 
+// Device layout of the two tables, one after the other.  FP64: row-major,
+// node (a, b) at a * 256 + b; the two nodes of a cell's row are adjacent, so
+// a cell is two 16-byte loads.  FP32-eval: row pairs, element 2 (a * 256 + b)
+// holding node (a, b) and the next one node (a + 1, b) (0 for a = 255), so a
+// cell's four nodes are four consecutive floats, one 16-byte load instead of
+// two 8-byte ones (2% faster; the same layout in FP64 measured 0.5% slower).
+template <typename R>
+constexpr int kTableStride = std::is_same<R, float>::value ? 2 * kTableN * kTableN : kTableN * kTableN;
+
 template <typename R>
 __device__ __forceinline__ TableCell<R> table_cell(const R *__restrict__ T, R x, R y) {
     const R ux = x * R(255), uy = y * R(255);
@@ -144,10 +153,20 @@ __device__ __forceinline__ TableCell<R> table_cell(const R *__restrict__ T, R x,
     TableCell<R> c;
     c.tx = ux - fa;
     c.ty = uy - fb;
-    c.t00 = T[cell];
-    c.t01 = T[cell + 1];
-    c.t10 = T[cell + kTableN];
-    c.t11 = T[cell + kTableN + 1];
+    if constexpr (std::is_same<R, float>::value) {
+        // two 8-byte-aligned pairs, which the compiler merges into one load
+        const float2 *q = reinterpret_cast<const float2 *>(T + 2 * cell);
+        const float2 lo = q[0], hi = q[1];
+        c.t00 = lo.x;
+        c.t10 = lo.y;
+        c.t01 = hi.x;
+        c.t11 = hi.y;
+    } else {
+        c.t00 = T[cell];
+        c.t01 = T[cell + 1];
+        c.t10 = T[cell + kTableN];
+        c.t11 = T[cell + kTableN + 1];
+    }
     return c;
 }
 
@@ -192,7 +211,7 @@ struct Integrand {
             if (j == 3) x3 = xj;
             if constexpr (EARLY) {
                 if (j == 1) c1 = table_cell(T, x0, x1);
-                if (j == 3) c2 = table_cell(T + kTableN * kTableN, x2, x3);
+                if (j == 3) c2 = table_cell(T + kTableStride<R>, x2, x3);
             }
         }
     }
@@ -217,7 +236,7 @@ struct Integrand {
             static_assert(D >= 4, "table integrand needs four axes");
             const R G = rexp(-acc);
             const R T1 = interpolate(EARLY ? c1 : table_cell(T, x0, x1));
-            const R T2 = interpolate(EARLY ? c2 : table_cell(T + kTableN * kTableN, x2, x3));
+            const R T2 = interpolate(EARLY ? c2 : table_cell(T + kTableStride<R>, x2, x3));
             return (G * T1) * T2;
         }
     }
