@@ -65,16 +65,21 @@ hipError_t launch_sample(int integrand, int dim, int blocks, int threads, size_t
                          hipStream_t stream, const SampleArgs &args);
 
 // Histogram accumulators of a V-Sample pass (a region of their own, so that
-// the totals of a pass with more workgroups never reach them): workgroup b adds its LDS histogram into accumulator b % kHistAcc
-// with device-scope FP64 atomics.  Eight copies cut the atomics that meet on
-// one address eightfold (workgroups are dispatched round-robin over the
-// chip's eight XCDs, so the copies also split by XCD); the finalize sums them
-// in order.
+// the totals of a pass with more workgroups never reach them): workgroup b
+// adds its LDS histogram into accumulator b % kHistAcc with device-scope
+// FP64 atomics.  Eight copies cut the atomics that meet on one address
+// eightfold (workgroups are dispatched round-robin over the chip's eight
+// XCDs, so the copies also split by XCD); they are summed in order after the
+// pass, by the finalize or by the steps kernel.
 constexpr int kHistAcc = 8;
 
 // Reduces the per-workgroup totals in a fixed order and sums the histogram
 // accumulators in order into out = [I, var, flag, 0, hist...]; clears the
-// accumulators (for the next pass) and the flag.
+// accumulators (for the next pass) and the flag.  (Runs whose steps between
+// passes are on the host.)
+hipError_t launch_finalize(const double *partials, double *hist_acc, int blocks, int nhist, int hist_stride,
+                           int with_hist, uint32_t *flag, double *out, hipStream_t stream);
+
 // A run whose steps between sampling passes (Weighted-Estimates,
 // Check-Convergence, Adjust-Bin-Bounds of Alg. 2) run on the device: its
 // state in the workspace, mirrored after every pass into page-locked host
@@ -92,9 +97,9 @@ struct RunState {
 };
 constexpr int32_t kRunGoing = 0, kRunConverged = 1, kRunNonFinite = 2;
 
-// The decision the finalize takes after pass it of such a run (state null:
-// none, the host takes it).  iters holds I_0 .. I_{itmax-1}, then var_0 ..
-// var_{itmax-1}, on the device; host_iters the same in the host mirror.
+// The decision after pass it of such a run.  iters holds I_0 .. I_{itmax-1},
+// then var_0 .. var_{itmax-1}, on the device; host_iters the same in the host
+// mirror (host, host_iters: mapped page-locked memory).
 struct RunCtl {
     RunState *state;
     double *iters;
@@ -104,25 +109,38 @@ struct RunCtl {
     double tau_rel, chi2_max;
 };
 
-hipError_t launch_finalize(const double *partials, double *hist_acc, int blocks, int nhist, int hist_stride,
-                           int with_hist, uint32_t *flag, double *out, const RunCtl &ctl,
-                           hipStream_t stream);
-
 // Start of a device-steps run: the state (last = itmax - 1, nothing done) and
 // Init-Bins (boundaries i/nb on every axis) in the workspace, and in
 // host_grid (mapped host memory) unless it is null.
 hipError_t launch_run_init(RunState *state, double *grid, double *host_grid, int d, int nb, int itmax,
                            hipStream_t stream);
 
-// Adjust-Bin-Bounds on the device after pass it of a device-steps run (nothing
-// if the run ended before it): one workgroup per axis (m-Cubes1D: axis 0, then
-// copied to every axis), the host's steps with sums in a fixed order of its
-// own and the device library's pow and log: the host's result to rounding.  Reads the histogram hist (d*nb), rewrites grid in place.
-// last may be null (no run: always adjusts).
-// host_grid (mapped host memory), unless null, receives the same boundaries.
-hipError_t launch_refine(double *grid, double *host_grid, const double *hist, int d, int nb, int one_d,
-                         double alpha, const int32_t *last, int it, hipStream_t stream);
-// LDS of one refinement workgroup, and the largest nb it takes.
+// Everything between pass ctl.it and the next of a device-steps run, one
+// launch: the totals merged and the decision taken (ctl), and in an
+// adjusting pass (nref = d, or 1 for m-Cubes1D; 0 otherwise) the grid
+// adjusted from the histogram accumulators, one workgroup per axis.
+struct StepsArgs {
+    RunCtl ctl;
+    const double *partials;   // the pass's per-workgroup totals
+    int32_t blocks;           // workgroups of the pass
+    int32_t hist_stride;
+    double *hist_acc;         // kHistAcc accumulators (cleared as they are read)
+    uint32_t *flag;           // non-finite flag (read and cleared)
+    double *grid;             // d*(nb+1) boundaries, adjusted in place
+    double *host_grid;        // mapped host copy of the boundaries, or null
+    double alpha;
+    int32_t d, nb, one_d, nref;
+};
+hipError_t launch_steps(const StepsArgs &args, hipStream_t stream);
+
+// Adjust-Bin-Bounds on the device (mc_refine_grid_device): one workgroup per
+// axis (m-Cubes1D: axis 0, then copied to every axis), the host's steps with
+// sums in a fixed order of its own and the device library's pow and log: the
+// host's result to rounding.  Reads the histogram hist (d*nb), rewrites grid
+// in place.
+hipError_t launch_refine(double *grid, const double *hist, int d, int nb, int one_d, double alpha,
+                         hipStream_t stream);
+// LDS of one adjusting workgroup, and the largest nb it takes.
 size_t refine_lds_bytes(int nb);
 constexpr int kDeviceStepsMaxBins = MC_DEVICE_STEPS_MAX_BINS;
 

@@ -255,7 +255,7 @@ mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_
     if (ev) HIP_TRY(hipEventRecord(ev->e[1], stream));
     double *out_dev = reinterpret_cast<double *>(ws + G.off_out);
     HIP_TRY(launch_finalize(a.partials, a.hist_acc, blocks, d * nb, G.hist_stride, adjust ? 1 : 0, a.flag,
-                            out_dev, RunCtl{}, stream));
+                            out_dev, stream));
     if (ev) HIP_TRY(hipEventRecord(ev->e[2], stream));
     if (adjust && d > 1 && !pr->one_d) AxisPool::get().prime(spin_us);
     HIP_TRY(hipMemcpyAsync(out_stage, out_dev, sizeof(double) * nout, hipMemcpyDeviceToHost, stream));
@@ -406,8 +406,7 @@ mc_status mc_refine_grid_device(int32_t dim, int32_t nbins, double alpha, int32_
     if (dim < 1 || dim > MC_MAX_DIM || nbins < 2 || nbins > kDeviceStepsMaxBins ||
         !(alpha > 0.0) || !std::isfinite(alpha) || (one_d != 0 && one_d != 1) || !d_hist || !d_grid)
         return MC_EINVAL;
-    HIP_TRY(launch_refine(d_grid, nullptr, d_hist, dim, nbins, one_d, alpha, nullptr, 0,
-                          static_cast<hipStream_t>(stream)));
+    HIP_TRY(launch_refine(d_grid, d_hist, dim, nbins, one_d, alpha, static_cast<hipStream_t>(stream)));
     return MC_OK;
 }
 
@@ -514,7 +513,6 @@ mc_status integrate_device(const mc_problem *prob, const Geometry &G, char *ws, 
     RunState *dst = reinterpret_cast<RunState *>(ws + G.off_run);
     double *iters = reinterpret_cast<double *>(dst + 1);
     double *grid = reinterpret_cast<double *>(ws + G.off_grid);
-    double *out_dev = reinterpret_cast<double *>(ws + G.off_out);
     double *partials = reinterpret_cast<double *>(ws + G.off_partials);
     double *hist_acc = reinterpret_cast<double *>(ws + G.off_hist);
     uint32_t *flag = reinterpret_cast<uint32_t *>(ws + G.off_flag);
@@ -535,16 +533,26 @@ mc_status integrate_device(const mc_problem *prob, const Geometry &G, char *ws, 
             return e;
         return timing ? hipEventRecord(ev->sampled[it % 3], s) : hipSuccess;
     };
-    // the rest of pass it: finalize and decision, bin adjustment, done marker
+    // the rest of pass it: totals, decision and bin adjustment in one launch,
+    // and with timing the done marker
     auto tail = [&](int it) -> hipError_t {
         const bool adjust = it < prob->ita;
-        const RunCtl ctl{dst, iters, hm_dev, h_its_dev, it, itmax, prob->tau_rel, prob->chi2_max};
-        hipError_t e = launch_finalize(partials, hist_acc, pass_blocks(it), d * nb, G.hist_stride,
-                                       adjust ? 1 : 0, flag, out_dev, ctl, s);
+        StepsArgs sa{};
+        sa.ctl = RunCtl{dst, iters, hm_dev, h_its_dev, it, itmax, prob->tau_rel, prob->chi2_max};
+        sa.partials = partials;
+        sa.blocks = pass_blocks(it);
+        sa.hist_stride = G.hist_stride;
+        sa.hist_acc = hist_acc;
+        sa.flag = flag;
+        sa.grid = grid;
+        sa.host_grid = mirror_grid;
+        sa.alpha = prob->alpha;
+        sa.d = d;
+        sa.nb = nb;
+        sa.one_d = prob->one_d;
+        sa.nref = adjust ? (prob->one_d ? 1 : d) : 0;
+        const hipError_t e = launch_steps(sa, s);
         if (e != hipSuccess) return e;
-        if (adjust && (e = launch_refine(grid, mirror_grid, out_dev + 4, d, nb, prob->one_d, prob->alpha,
-                                         &dst->last, it, s)) != hipSuccess)
-            return e;
         return timing ? hipEventRecord(done[it % 3], s) : hipSuccess;
     };
     // until pass it's decision is in the mirror: with timing, the pass's done

@@ -1,7 +1,7 @@
 // The steps of Alg. 2 between two sampling passes, on the device, for runs
-// that keep them there: the start of a run (Init-Bins and the run state) and
-// Adjust-Bin-Bounds.  Weighted-Estimates and Check-Convergence follow each
-// pass in the finalize kernel.
+// that keep them there: the start of a run (Init-Bins and the run state), and
+// after each pass one launch that merges the pass's results, runs
+// Weighted-Estimates and Check-Convergence, and Adjust-Bin-Bounds.
 //
 // The bin adjustment takes the host's steps (three-point smoothing, Lepage's
 // damped compression, equal shares of the compressed weight per new bin)
@@ -16,12 +16,14 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "merge.hpp"
 
 namespace mcubes {
 
 namespace {
 
 constexpr int kRefineThreads = 256;
+static_assert(kRefineThreads == merge::kThreads, "the steps kernel's last workgroup merges the totals");
 
 // The workgroup's threads each take a contiguous run of [first, last): the
 // run of thread t.
@@ -133,19 +135,18 @@ __global__ void __launch_bounds__(256) run_init_kernel(RunState *st, double *gri
     if (host_grid) __threadfence_system();
 }
 
-// One workgroup per axis j (m-Cubes1D: one, for axis 0).  LDS: the
-// compressed weights r (nb), their running sums P (nb + 1), the old
-// boundaries (nb + 1) and the new ones (nb + 1).  host_grid, if not null,
-// receives every boundary written to grid.
-__global__ void __launch_bounds__(kRefineThreads)
-refine_kernel(double *grid, double *host_grid, const double *hist, int d, int nb, int one_d,
-              double alpha, const int32_t *last, int it) {
-    if (last && it > *last) return;  // the run ended before this pass
-    extern __shared__ double lds[];
+// Adjust-Bin-Bounds of axis j by one workgroup of kRefineThreads.  On entry
+// C (nb doubles, in LDS or device memory) holds the axis's contributions and
+// the LDS arrays follow lds: the compressed weights r (nb), their running
+// sums P (nb + 1), the old boundaries (nb + 1) and the new ones E (nb + 1).
+// grid row j is rewritten in place (m-Cubes1D, j = 0: and copied to every
+// axis); host_grid, if not null, receives every boundary written to grid.
+// C may be E itself: it is read before E is written.
+__device__ __forceinline__ void adjust_axis(double *lds, const double *C, double *grid, double *host_grid, int j, int d,
+                            int nb, int one_d, double alpha) {
     double *r = lds, *P = r + nb, *prev = P + nb + 1, *E = prev + nb + 1;
     __shared__ double wave_tmp[kRefineThreads / 64];
-    const int tid = threadIdx.x, j = blockIdx.x;
-    const double *C = hist + (size_t)j * nb;
+    const int tid = threadIdx.x;
     double *B = grid + (size_t)j * (nb + 1);
     for (int i = tid; i <= nb; i += kRefineThreads) prev[i] = B[i];
     // three-point smoothing (two points at the ends)
@@ -213,6 +214,42 @@ refine_kernel(double *grid, double *host_grid, const double *hist, int d, int nb
     if (host_grid) __threadfence_system();
 }
 
+// mc_refine_grid_device: one workgroup per axis (m-Cubes1D: one), the
+// contributions read from hist.
+__global__ void __launch_bounds__(kRefineThreads)
+refine_kernel(double *grid, const double *hist, int d, int nb, int one_d, double alpha) {
+    extern __shared__ double lds[];
+    adjust_axis(lds, hist + (size_t)blockIdx.x * nb, grid, nullptr, blockIdx.x, d, nb, one_d, alpha);
+}
+
+// Everything between pass it and the next of a device-steps run, in one
+// launch (nothing once the run has ended before pass it).  Workgroups
+// [0, nref) adjust one axis each (nref = 0 in a No-Adjust pass), taking the
+// axis's contributions from the histogram accumulators (summed in order and
+// cleared, as the finalize does); workgroup nref merges the totals and takes
+// the pass's decision.  The adjustment of pass it does not depend on that
+// decision (a run refines after its last adjusting pass too).
+__global__ void __launch_bounds__(kRefineThreads) steps_kernel(const StepsArgs A) {
+    if (A.ctl.it > A.ctl.state->last) return;  // (this launch sets last to it at most)
+    extern __shared__ double lds[];
+    if ((int)blockIdx.x < A.nref) {
+        const int j = blockIdx.x, nb = A.nb;
+        double *C = lds + 3 * (size_t)nb + 2;  // the E array, free until the search
+        for (int i = threadIdx.x; i < nb; i += kRefineThreads)
+            C[i] = merge::take_bin(A.hist_acc, (size_t)j * nb + i, A.hist_stride);
+        __syncthreads();
+        adjust_axis(lds, C, A.grid, A.host_grid, j, A.d, nb, A.one_d, A.alpha);
+        return;
+    }
+    double I = 0.0, V = 0.0;
+    merge::pass_totals(A.partials, A.blocks, &I, &V);
+    if (threadIdx.x == 0) {
+        const bool bad = *A.flag != 0u;
+        *A.flag = 0u;
+        merge::decide(A.ctl, I, V, bad);
+    }
+}
+
 }  // namespace
 
 size_t refine_lds_bytes(int nb) { return sizeof(double) * (4 * (size_t)nb + 3); }
@@ -224,8 +261,8 @@ hipError_t launch_run_init(RunState *state, double *grid, double *host_grid, int
     return hipGetLastError();
 }
 
-hipError_t launch_refine(double *grid, double *host_grid, const double *hist, int d, int nb, int one_d,
-                         double alpha, const int32_t *last, int it, hipStream_t stream) {
+hipError_t launch_refine(double *grid, const double *hist, int d, int nb, int one_d, double alpha,
+                         hipStream_t stream) {
     const size_t lds = refine_lds_bytes(nb);
     if (lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&refine_kernel),
@@ -233,7 +270,18 @@ hipError_t launch_refine(double *grid, double *host_grid, const double *hist, in
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(refine_kernel, dim3(one_d ? 1 : d), dim3(kRefineThreads), lds, stream, grid,
-                       host_grid, hist, d, nb, one_d, alpha, last, it);
+                       hist, d, nb, one_d, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps(const StepsArgs &args, hipStream_t stream) {
+    const size_t lds = args.nref ? refine_lds_bytes(args.nb) : 0;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&steps_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(steps_kernel, dim3(args.nref + 1), dim3(kRefineThreads), lds, stream, args);
     return hipGetLastError();
 }
 
