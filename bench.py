@@ -320,6 +320,39 @@ def cpu_baseline(prob, target_s: float = 6.0, max_workers: int = 16, tau_rel: fl
                              "estimate": est, "rel_error": err / abs(est) if est else None}}
 
 
+def cpu_baseline_sample(prob, target_s: float = 4.0, max_workers: int = 16):
+    """The FP64 oracle on a bounded sample of a configuration too large for a
+    whole pass: one core on a block of sub-cubes (iteration 0, uniform grid,
+    histogram on) for the per-core rate, then the first B sub-cubes, B sized
+    from that rate for about target_s, split into one block per worker
+    process.  Runs before the GPU is touched (fork)."""
+    import multiprocessing as mp
+
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+
+    d, nb = prob["dim"], prob["nbins"]
+    g, m, p = O.shape(d, prob["maxcalls"])
+    grid0 = O.init_grid(d, nb)
+    n = min(m, 20_000)
+    dt = _oracle_block((prob, 0, grid0, 0, n, True))[3]
+    usable, reported, model = _host_cpus()
+    workers = max(1, min(usable, max_workers))
+    B = int(min(m, max(workers, n / max(dt, 1e-6) * workers * target_s)))
+    cuts = [B * k // workers for k in range(workers + 1)]
+    jobs = [(prob, 0, grid0, cuts[k], cuts[k + 1], True) for k in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        t = time.perf_counter()
+        pool.map(_oracle_block, jobs)
+        wall = time.perf_counter() - t
+    return {"value": B * p / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
+            "sample": f"one FP64 V-Sample pass of iteration 0 over the first {B} of the {m} sub-cubes "
+                      f"({B * p} samples, uniform grid, histogram on) split into {workers} blocks on "
+                      f"{workers} processes: {wall:.2f} s wall; one core alone: {n * p} samples in {dt:.2f} s",
+            "single_core": n * p / dt,
+            "host": {"cpus_usable": usable, "cpus_reported": reported, "cpu_model": model}}
+
+
 def _base_line(args, name, value, ms_per_step, dtype, config):
     return {"metric": "integrand samples/sec/GPU", "value": value, "unit": "samples/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -573,6 +606,10 @@ def main():
     if args.workload in WORKLOADS and WORKLOADS[args.workload][1] is not None and not args.no_cpu_baseline:
         from paper_2202_01753_amd import workloads as W0
         cpu = cpu_baseline(WORKLOADS[args.workload][1](W0, 1))
+    cpu8 = None
+    if args.workload == "tables" and not args.no_corner8 and not args.no_cpu_baseline:
+        from paper_2202_01753_amd import workloads as W0
+        cpu8 = cpu_baseline_sample(W0.config_corner8(seed=1))
 
     import torch
 
@@ -653,6 +690,8 @@ def main():
             sub["fp64" if prec == "fp64" else "fp32_eval"] = r
         sub["config"] = {"dim": 8, "maxcalls": c8["maxcalls"], "calls_per_iter": sub["fp64"]["calls_per_iter"],
                          "nbins": c8["nbins"], "itmax": c8["itmax"], "steps": k}
+        if cpu8 is not None:
+            sub["cpu_baseline"] = cpu8
         line["corner_peak_d8_1e9"] = sub
     if cpu is not None:
         line["cpu_baseline"] = cpu

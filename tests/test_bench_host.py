@@ -88,6 +88,15 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr
 
 
+def test_cpu_baseline_sample_times_a_bounded_block():
+    """The CPU leg for a configuration too large for a whole pass: the first B
+    sub-cubes over worker processes, B sized from the per-core rate."""
+    prob = W.corner_peak(4, 3, maxcalls=2_000_000, nbins=50, itmax=2)
+    r = B.cpu_baseline_sample(prob, target_s=0.05, max_workers=2)
+    assert r["kind"] == "oracle" and r["value"] > 0 and 1 <= r["cores"] <= 2
+    assert "sub-cubes" in r["sample"] and r["single_core"] > 0
+
+
 def test_cpu_baseline_runs_the_oracle_on_the_host():
     """The CPU leg on the small configuration: a pass over all sub-cubes split
     across worker processes, a run to 1e-3, and the host's CPUs recorded."""
