@@ -488,11 +488,11 @@ hipError_t run_events(RunEvents **out) {
 }
 
 // Alg. 2 with its steps between passes on the device: Init-Bins and the run
-// state, then per pass the sampling kernel, the finalize (totals, histogram,
-// Weighted-Estimates, Check-Convergence) and, while adjusting, the bin
-// adjustment, all on the stream.  The sampling kernel of the next pass is
+// state, then per pass the sampling kernel and one steps launch (totals,
+// Weighted-Estimates, Check-Convergence and, while adjusting, the bin
+// adjustment), all on the stream.  The sampling kernel of the next pass is
 // always queued before the host waits for a pass, so the device never waits
-// for the host; the rest of that pass is queued once the decision of the
+// for the host; the steps of that pass are queued once the decision of the
 // pass before is known, so a run that converges leaves only one sampling
 // launch queued behind it, which does nothing.  The decisions, the
 // per-iteration results and the grid come back through the mapped mirror.
@@ -556,7 +556,7 @@ mc_status integrate_device(const mc_problem *prob, const Geometry &G, char *ws, 
         return timing ? hipEventRecord(done[it % 3], s) : hipSuccess;
     };
     // until pass it's decision is in the mirror: with timing, the pass's done
-    // marker; otherwise the mirror's pass count, which the finalize writes
+    // marker; otherwise the mirror's pass count, which the steps kernel writes
     // last (no marker, which would hold the stream for a few microseconds),
     // with a look at the stream now and then, so that an error or a stream
     // that has run dry ends the wait
