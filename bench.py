@@ -348,7 +348,7 @@ def cpu_baseline_sample(prob, target_s: float = 4.0, max_workers: int = 16):
     return {"value": B * p / wall, "unit": "samples/s", "cores": workers, "kind": "oracle",
             "sample": f"one FP64 V-Sample pass of iteration 0 over the first {B} of the {m} sub-cubes "
                       f"({B * p} samples, uniform grid, histogram on) split into {workers} blocks on "
-                      f"{workers} processes: {wall:.2f} s wall; one core alone: {n * p} samples in {dt:.2f} s",
+                      f"{workers} processes: {wall:.2f} s wall; one core alone: {n * p} samples in {dt * 1e3:.1f} ms",
             "single_core": n * p / dt,
             "host": {"cpus_usable": usable, "cpus_reported": reported, "cpu_model": model}}
 
