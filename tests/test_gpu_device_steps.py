@@ -228,3 +228,23 @@ def test_device_steps_on_two_streams():
     assert not errors and all(not t.is_alive() for t in threads)
     for a, b in zip(out, alone):
         _same_run(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("config", ["tables_d6_1e8", "corner_peak_d8_1e9"])
+def test_device_steps_at_benchmark_size(config, precision):
+    """The benchmarked runs themselves (all passes, the launch shapes the
+    benchmark uses) with the steps on the device against the same runs with
+    the steps on the host, whose passes the lockstep and whole-pass tests hold
+    to the oracle: same iterations, per-iteration estimates within 1e-11,
+    grids within 1e-12."""
+    if config == "tables_d6_1e8":
+        prob = W.config_tables(seed=3, precision=precision)
+    else:
+        prob = W.config_corner8(seed=3, precision=precision)
+    host = M.integrate(prob)
+    dev = M.integrate(_dev(prob), timing=True)
+    print(config, precision, "iterations", dev.iterations, "estimate", dev.estimate, "+-", dev.error,
+          "sample ms/pass", dev.sample_ms / dev.iterations, flush=True)
+    _same_run(dev, host)
+    assert abs(dev.estimate - CF.exact(prob)) < 5 * dev.error
