@@ -1,5 +1,5 @@
 // Internal interface between the host driver (mcubes_api.cpp) and the HIP
-// kernels (vsample_*.hip, finalize.hip).  Not part of the C ABI.
+// kernels (vsample_*.hip, finalize.hip, steps.hip).  Not part of the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -52,10 +52,10 @@ mc_status blocks_for(const void *fn, int threads, size_t lds, int64_t m, int req
     // later, instead of idling for the rest of the launch (four times as many:
     // 12% faster at d = 8 with two 768-thread workgroups per CU; one 1024-thread
     // workgroup per CU gains nothing and keeps the resident count).  Every
-    // workgroup also leaves a histogram partial for the finalize to read, so
-    // four times is taken only where each lane still has at least 100
-    // sub-cubes to do, twice otherwise (the FP32 d = 6 tables pass: 60 per
-    // lane at twice; at four times its merge took 31 us of a 0.66 ms pass).
+    // workgroup also ends with a flush of its histogram, so four times is
+    // taken only where each lane still has at least 100 sub-cubes to do,
+    // twice otherwise (the FP32 d = 6 tables pass: 60 per lane at twice;
+    // once, twice and four times measured 0.632, 0.615 and 0.616 ms).
     const int64_t resident = (int64_t)per_cu * cus;
     int64_t want = resident;
     if (requested > 0)
@@ -199,8 +199,6 @@ struct Events {
     }
 };
 
-// Runs sampling + finalize and reads the result back.  out_host holds
-// 4 + d*nb doubles.
 // Page-locked staging for the calling thread's passes (grid up, results
 // down), grown on demand and kept until the process ends, so that both copies
 // are direct DMA rather than staged through pageable memory.
@@ -223,9 +221,11 @@ hipError_t pass_stage(size_t bytes, char **out) {
     return hipSuccess;
 }
 
-// pinned: stage the grid and the results through page-locked memory (direct
-// DMA; allocated on first use); otherwise copy from and to the caller's
-// pageable buffers, which allocates nothing.
+// One pass with the steps on the host: sampling + finalize, and the result
+// read back into out_host (4 + d*nb doubles).  pinned: stage the grid and
+// the results through page-locked memory (direct DMA; allocated on first
+// use); otherwise copy from and to the caller's pageable buffers, which
+// allocates nothing.
 mc_status run_pass(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t stream,
                    uint32_t iter, bool adjust, const double *h_grid, double *out_host,
                    double *trace, int64_t t0, int64_t t1, Events *ev, double *ms_sample,
@@ -294,8 +294,8 @@ mc_status prepare(const mc_problem *pr, const Geometry &G, char *ws, hipStream_t
                                    hipMemcpyHostToDevice, stream));
     }
     HIP_TRY(launch_clear_flag(reinterpret_cast<uint32_t *>(ws + G.off_flag), stream));
-    // the histogram accumulators start at zero; each adjusting pass's finalize
-    // clears them again after reading them
+    // the histogram accumulators start at zero; the finalize or steps kernel
+    // of each adjusting pass clears them again after reading them
     HIP_TRY(launch_zero(reinterpret_cast<double *>(ws + G.off_hist),
                         (size_t)kHistAcc * G.hist_stride, stream));
     HIP_TRY(hipStreamSynchronize(stream));

@@ -16,7 +16,7 @@
 // with error-free transformations.  Per workgroup: a fixed-order wave and
 // workgroup reduction, then the totals go to this workgroup's slot of the
 // partials array and the LDS histogram is added into one of the histogram
-// accumulators, both for the finalize kernel.
+// accumulators, both merged after the pass (finalize or steps kernel).
 #pragma once
 
 #include <type_traits>
