@@ -132,6 +132,9 @@ CASES = [
          name="tables d6 fp32"),
     dict(make=lambda: W.symmetric_corner(6, a=1.0, maxcalls=400_000, nbins=200, itmax=5, one_d=1, seed=4),
          name="m-Cubes1D"),
+    dict(make=lambda: W.gauss_product(3, 12, maxcalls=100_000, nbins=50, itmax=4, ita=0, seed=6),
+         name="no adjusting pass"),
+    dict(make=lambda: W.corner_peak(4, 13, maxcalls=100_000, nbins=64, itmax=1, seed=7), name="one pass"),
 ]
 
 
