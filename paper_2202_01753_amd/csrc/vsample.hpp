@@ -309,6 +309,19 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
         for (int i = tid; i < D * nb * a.hist_copies; i += nthr) v.hist[i] = 0.0;
 }
 
+// Whether the one-sample path computes every axis's bin and issues every
+// grid read before the rest of the sample (GF in cube_pass).  Each axis's
+// constants are scalar loads whose wait also waits for the LDS reads in
+// flight, so axis by axis every grid read was waited for on its own; in two
+// phases they overlap.  Taken for the FP64 Gaussian and table kernels where
+// the values held across the phases keep the occupancy and add no spill:
+// 3-4% faster at d = 4, 2-3% at d = 6 to 8 (the d = 6 table kernel 1.024 ->
+// 0.993 ms), 1% for the tables at d = 7; the corner-peak kernels lose
+// occupancy (d = 8: 9% slower) and d >= 10 would spill.
+template <int F, int D, bool F32>
+constexpr bool kGridFirst =
+    !F32 && ((F == 1 && (D == 3 || D == 4 || (D >= 6 && D <= 9))) || (F == 3 && D >= 4 && D <= 7));
+
 // Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
 // independent evaluations interleave and hide each other's LDS and
 // transcendental latency, but both must fit in registers: in FP32 evaluation
@@ -362,8 +375,8 @@ constexpr int kFixedWaves =
 // they are read with the other constants.  (A compile-time choice: a null
 // pointer tested at run time, though folded away, changed the FP32 d = 8
 // kernels' register allocation from 72 to 90.)
-template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, bool LOV = false, typename A,
-          typename CP>
+template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, bool LOV = false, bool GF = false,
+          typename A, typename CP>
 __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad, const real_t<F32> *lov = nullptr) {
@@ -507,27 +520,54 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
             Integrand<F, D, R, EARLY> fx(a.tables);
             int bin[D];
             R J = R(1);
+            // GF: every axis's bin and grid read first, then the rest axis by
+            // axis, so that the grid reads are in flight together rather
+            // than each waited for before the next is issued (see kGridFirst)
+            R gf_frac[GF ? D : 1], gf_left[GF ? D : 1], gf_right[GF ? D : 1];
+            int gf_bin[GF ? D : 1];
+            if constexpr (GF) {
+                static_assert(!F32, "two-phase axes are an FP64 layout");
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const R z = (cd[j] + uniform53(w[j], w[D + j])) * s;
+                    const R fz = rmin(rfloor(z), last);
+                    gf_bin[j] = (int)fz;
+                    gf_frac[j] = rmin(z - fz, R(1));
+                    const R *B = sG + j * row + gf_bin[j];
+                    gf_left[j] = B[0];
+                    gf_right[j] = B[1];
+                }
+                __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of their uses
+            }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                R u;
-                if constexpr (F32) u = uniform24(w[j]);
-                else u = uniform53(w[j], w[D + j]);
-                const R z = (cd[j] + u) * s;
-                // bin index, clamped to the last bin with fraction 1 there: once
-                // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
-                // gives exactly 1; otherwise z - floor(z) < 1 is exact.
-                const R fz = rmin(rfloor(z), last);
-                const int i = (int)fz;
-                const R frac = rmin(z - fz, R(1));
-                R left, width;
-                if constexpr (F32) {
-                    const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
-                    left = cell.x;
-                    width = cell.y;
+                R u = R(0), frac, left, width;
+                int i;
+                if constexpr (GF) {
+                    if (traced) u = uniform53(w[j], w[D + j]);
+                    i = gf_bin[j];
+                    frac = gf_frac[j];
+                    left = gf_left[j];
+                    width = gf_right[j] - left;
                 } else {
-                    const R *B = sG + j * row + i;
-                    left = B[0];
-                    width = B[1] - left;
+                    if constexpr (F32) u = uniform24(w[j]);
+                    else u = uniform53(w[j], w[D + j]);
+                    const R z = (cd[j] + u) * s;
+                    // bin index, clamped to the last bin with fraction 1 there: once
+                    // floor(z) > nb-1 we have z >= nb, so z - (nb-1) >= 1 and the min
+                    // gives exactly 1; otherwise z - floor(z) < 1 is exact.
+                    const R fz = rmin(rfloor(z), last);
+                    i = (int)fz;
+                    frac = rmin(z - fz, R(1));
+                    if constexpr (F32) {
+                        const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + i];
+                        left = cell.x;
+                        width = cell.y;
+                    } else {
+                        const R *B = sG + j * row + i;
+                        left = B[0];
+                        width = B[1] - left;
+                    }
                 }
                 const R xu = rfma(frac, width, left);
                 const auto cj = axis_consts<kBatchConsts>(sC, j);
@@ -686,7 +726,8 @@ __global__ void __launch_bounds__(kMaxBlock)
     }
     while (t < (uint64_t)a.m) {
         double It, vt;
-        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true, kLowInVgpr<F, D, F32>>(
+        cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true, kLowInVgpr<F, D, F32>,
+                  kGridFirst<F, D, F32>>(
             a, v, sC, t, dig, It, vt, bad, lov);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
