@@ -317,8 +317,9 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
 // the values held across the phases keep the occupancy and add no spill:
 // 3-4% faster at d = 4, 2-3% at d = 6 to 8 (the d = 6 table kernel 1.024 ->
 // 0.993 ms), 1% for the tables at d = 7; the corner-peak kernels lose
-// occupancy (d = 8: 9% slower), d >= 10 would spill, and the FP32-eval
-// table kernel, held at 71 VGPRs for 6 waves per SIMD, ran 3% slower.
+// occupancy (d = 8: 9% slower; 4% with the priority hint of cube_pass),
+// d >= 10 would spill, and the FP32-eval table kernel, held at 71 VGPRs for
+// 6 waves per SIMD, ran 3% slower (as fast with the priority hint).
 template <int F, int D, bool F32>
 constexpr bool kGridFirst =
     !F32 && ((F == 1 && (D == 3 || D == 4 || (D >= 6 && D <= 9))) || (F == 3 && D >= 4 && D <= 7));
