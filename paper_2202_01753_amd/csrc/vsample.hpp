@@ -376,9 +376,11 @@ constexpr int kFixedWaves =
 // holds the axes' lower bounds in vector registers (kLowInVgpr); otherwise
 // they are read with the other constants.  (A compile-time choice: a null
 // pointer tested at run time, though folded away, changed the FP32 d = 8
-// kernels' register allocation from 72 to 90.)
+// kernels' register allocation from 72 to 90.)  GF: see kGridFirst.  PRIO:
+// the one-sample path raises the wave's priority for the first part of each
+// sample (the pair path always does).
 template <int F, int D, bool TRACE, bool F32, bool PAIR, bool EARLY, bool LOV = false, bool GF = false,
-          typename A, typename CP>
+          bool PRIO = false, typename A, typename CP>
 __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP sC, uint64_t t,
                                           const uint32_t (&dig)[D], double &It, double &vt,
                                           bool &bad, const real_t<F32> *lov = nullptr) {
@@ -515,14 +517,16 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
         // batched kernel, which inlines every case, allocates fewer registers
         // for this form than for the lambda one
         for (int k = 0; k < a.p; ++k) {
-            // GF: the wave runs at raised priority from the start of a sample
-            // until phase 1 has issued its grid reads.  s_setprio only orders
-            // issue among the waves of a SIMD; favouring the waves that are
-            // still on their way to their reads puts more reads in flight
-            // while the others compute (FP64 table and Gaussian kernels 2-4%
-            // faster; the one-phase kernels of this path, FP64 corner peak and
-            // FP32-eval tables at d = 6, gained nothing or lost up to 2%)
-            if constexpr (GF) __builtin_amdgcn_s_setprio(1);
+            // PRIO: the wave runs at raised priority from the start of a
+            // sample until its integrand value.  s_setprio only orders issue
+            // among the waves of a SIMD; favouring the waves that are still on
+            // their way to their grid reads and table loads puts more of them
+            // in flight while the others compute.  Taken with the two phases
+            // (FP64 table and Gaussian kernels 2-5% faster) and in the
+            // batched kernel (FP32-eval 1%); the one-phase single-integral
+            // kernels of this path, FP64 corner peak and FP32-eval tables at
+            // d = 6, gained nothing or lost up to 2%.
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
             uint32_t w[4 * NUSED];
 #pragma unroll
             for (int b = 0; b < NUSED; ++b) {
@@ -554,7 +558,6 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                     gf_right[j] = B[1];
                 }
                 __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of their uses
-                __builtin_amdgcn_s_setprio(0);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -603,6 +606,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                     r[2 * D + j] = (double)xj;
                 }
             }
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
             const R f = fx.value(a);
             const double Fv = (double)f * (double)J;
             bad |= !isfinite(Fv);
@@ -744,7 +748,7 @@ __global__ void __launch_bounds__(kMaxBlock)
     while (t < (uint64_t)a.m) {
         double It, vt;
         cube_pass<F, D, TRACE, F32, kPairSamples<F, D, F32>, true, kLowInVgpr<F, D, F32>,
-                  kGridFirst<F, D, F32>>(
+                  kGridFirst<F, D, F32>, kGridFirst<F, D, F32>>(
             a, v, sC, t, dig, It, vt, bad, lov);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);

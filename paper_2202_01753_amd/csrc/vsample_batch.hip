@@ -44,8 +44,10 @@ __device__ __forceinline__ void run_segment(Const<SampleArgs> &a, const BatchSeg
     while (t < (uint64_t)sg.t1) {
         double It, vt;
         // (plain, not volatile, constant loads: measured faster here, where
-        // the cases' shared register allocation is set by other values)
-        cube_pass<F, D, false, F32, false, false>(a, v, (Const<real_t<F32>> *)a.consts, t, dig, It, vt, bad);
+        // the cases' shared register allocation is set by other values; one
+        // phase, raised priority for the first part of each sample)
+        cube_pass<F, D, false, F32, false, false, false, false, true>(a, v, (Const<real_t<F32>> *)a.consts, t, dig,
+                                                                      It, vt, bad);
         two_sum_add(sI, cI, It);
         two_sum_add(sV, cV, vt);
         t += blockDim.x;
