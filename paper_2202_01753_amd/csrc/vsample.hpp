@@ -522,11 +522,12 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
             // among the waves of a SIMD; favouring the waves that are still on
             // their way to their grid reads and table loads puts more of them
             // in flight while the others compute.  Taken with the two phases
-            // (FP64 table and Gaussian kernels 2-5% faster) and in the
+            // (FP64 table and Gaussian kernels 2-5% faster), where phase 1
+            // runs a level higher still (another 0.3-1.2%), and in the
             // batched kernel (FP32-eval 1%); the one-phase single-integral
             // kernels of this path, FP64 corner peak and FP32-eval tables at
             // d = 6, gained nothing or lost up to 2%.
-            if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
+            if constexpr (PRIO) __builtin_amdgcn_s_setprio(GF ? 2 : 1);
             uint32_t w[4 * NUSED];
 #pragma unroll
             for (int b = 0; b < NUSED; ++b) {
@@ -558,6 +559,7 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                     gf_right[j] = B[1];
                 }
                 __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of their uses
+                if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j) {
