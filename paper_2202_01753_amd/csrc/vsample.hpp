@@ -316,13 +316,15 @@ __device__ __forceinline__ void load_lds(const A &a, const LdsView<F32> &v) {
 // phases they overlap.  Taken for the FP64 Gaussian and table kernels where
 // the values held across the phases keep the occupancy and add no spill:
 // 3-4% faster at d = 4, 2-3% at d = 6 to 8 (the d = 6 table kernel 1.024 ->
-// 0.993 ms), 1% for the tables at d = 7; the corner-peak kernels lose
-// occupancy (d = 8: 9% slower; 4% with the priority hint of cube_pass),
-// d >= 10 would spill, and the FP32-eval table kernel, held at 71 VGPRs for
-// 6 waves per SIMD, ran 3% slower (as fast with the priority hint).
+// 0.993 ms), 1% for the tables at d = 7, and for the FP32-eval table kernel
+// at d = 6 together with the priority hint of cube_pass held until the
+// integrand value (1.5%; 3% slower without the hint); the corner-peak
+// kernels lose occupancy (d = 8: 9% slower; 4% with the hint), and d >= 10
+// would spill.
 template <int F, int D, bool F32>
 constexpr bool kGridFirst =
-    !F32 && ((F == 1 && (D == 3 || D == 4 || (D >= 6 && D <= 9))) || (F == 3 && D >= 4 && D <= 7));
+    (!F32 && ((F == 1 && (D == 3 || D == 4 || (D >= 6 && D <= 9))) || (F == 3 && D >= 4 && D <= 7))) ||
+    (F32 && F == 3 && D == 6);
 
 // Whether cube_pass evaluates the samples of a sub-cube two at a time.  Two
 // independent evaluations interleave and hide each other's LDS and
@@ -547,16 +549,24 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
             R gf_frac[GF ? D : 1], gf_left[GF ? D : 1], gf_right[GF ? D : 1];
             int gf_bin[GF ? D : 1];
             if constexpr (GF) {
-                static_assert(!F32, "two-phase axes are an FP64 layout");
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    const R z = (cd[j] + uniform53(w[j], w[D + j])) * s;
+                    R uj;
+                    if constexpr (F32) uj = uniform24(w[j]);
+                    else uj = uniform53(w[j], w[D + j]);
+                    const R z = (cd[j] + uj) * s;
                     const R fz = rmin(rfloor(z), last);
                     gf_bin[j] = (int)fz;
                     gf_frac[j] = rmin(z - fz, R(1));
-                    const R *B = sG + j * row + gf_bin[j];
-                    gf_left[j] = B[0];
-                    gf_right[j] = B[1];
+                    if constexpr (F32) {
+                        const float2 cell = reinterpret_cast<const float2 *>(sG)[j * nb + gf_bin[j]];
+                        gf_left[j] = cell.x;
+                        gf_right[j] = cell.y;  // FP32-eval grids hold the width here
+                    } else {
+                        const R *B = sG + j * row + gf_bin[j];
+                        gf_left[j] = B[0];
+                        gf_right[j] = B[1];
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of their uses
                 if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
@@ -566,11 +576,15 @@ __device__ __forceinline__ void cube_pass(const A &a, const LdsView<F32> &v, CP 
                 R u = R(0), frac, left, width;
                 int i;
                 if constexpr (GF) {
-                    if (traced) u = uniform53(w[j], w[D + j]);
+                    if (traced) {
+                        if constexpr (F32) u = uniform24(w[j]);
+                        else u = uniform53(w[j], w[D + j]);
+                    }
                     i = gf_bin[j];
                     frac = gf_frac[j];
                     left = gf_left[j];
-                    width = gf_right[j] - left;
+                    if constexpr (F32) width = gf_right[j];
+                    else width = gf_right[j] - left;
                 } else {
                     if constexpr (F32) u = uniform24(w[j]);
                     else u = uniform53(w[j], w[D + j]);
